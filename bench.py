@@ -1,0 +1,198 @@
+"""Benchmark of the upscaled Brinkman LBM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (the fine-grid configuration the throughput metric is quoted on):
+D2Q9 BGK Brinkman LBM with the Shan-Chen velocity-shift force on a 2048 x 2048
+grid, log-normal permeability K = exp(Z) (Z a seeded periodic Gaussian random
+field, sigma 1.5, correlation length 32 cells), porosity 0.4, tau 0.8,
+nu = nu_eff = 0.1, g = 1e-6 along x, bounce-back walls in y, FP32 deviation
+populations. One step = one fused collide-and-stream pass; the volume-averaged
+velocity (FP64 reduction) is taken every 100 steps inside the timed region.
+
+Printed: one JSON line with MLUPS (value), the HBM roofline of the step kernel
+measured live with HIP events, the batched local K_eff throughput (patches/s)
+on the 4096 32 x 32 tiles of the same field plus 4096 mixed-size patches, and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (D2Q9 Brinkman, % HBM roofline); K_eff patches/s surrogate vs LBM @2%"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LU = 76  # 9 x 4 B read + 9 x 4 B written + 4 B drag coefficient
+STEP_KERNEL_SRC = os.path.join(ROOT, "paper_1312_0195_amd", "csrc", "lbm_fine.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fine_step_2048_hbm_counters.md")
+
+
+def _src_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def _traffic_per_launch():
+    """HBM bytes per step-kernel launch from the committed counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    txt = open(TRAFFIC_SUMMARY).read()
+    m_src = re.search(r"kernel source sha256\[:16\]:\s*([0-9a-f]{16})", txt)
+    m_b = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
+    if not m_src or not m_b or m_src.group(1) != _src_hash(STEP_KERNEL_SRC):
+        return None
+    return float(m_b.group(1))
+
+
+def bench_fine(L, torch, kappa, steps, warmup, check_every=100):
+    n = kappa.shape[0]
+    p = L.make_params(n, n, 0.8, 0.4, 0.1, 1.0, 1e-6, 0.0, 1, L.LBM_F32_SHIFTED)
+    s = L.FineSolver(p, kappa)
+    stream = torch.cuda.current_stream()
+    # warm-up: the same mix of step and reduction kernels
+    s.step(warmup, 0.0, check_every)
+    torch.cuda.synchronize()
+    # timed region: K steps with the FP64 mean-velocity reduction every 100 steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    st, done, mu = s.step(steps, 0.0, check_every)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    assert st == L.LBM_OK and done == steps and np.isfinite(mu).all()
+    # step kernel alone: back-to-back launches, no reductions, same stream
+    k = min(steps, 2000)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record(stream)
+    s.step(k, 0.0, 0)
+    e3.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e2.elapsed_time(e3) / k
+    s.close()
+    return dict(wall_s=wall, event_ms=ev_ms, step_kernel_ms=step_ms, mean_u=mu.tolist())
+
+
+def bench_local(L, torch, kappa_dev, reps=3):
+    from paper_1312_0195_amd import inputs as I
+    n = kappa_dev.shape[0]
+    out = {}
+    sets = {"tiles32": I.tile_patches(n, n, 32), "mixed": I.mixed_patches(4096, n, n, seed=1)}
+    for name, (x0, y0, side) in sets.items():
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = L.local_keff(None, x0, y0, side, 0.8, 0.4, 0.1, 1e-6, tol=1e-7, check_every=100,
+                             max_steps=400000, kappa_dev=kappa_dev)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        lu = float(np.sum(r.steps.astype(np.float64) * (side.astype(np.float64) ** 2)[:, None]))
+        out[name] = dict(patches=int(len(x0)), seconds=best, patches_per_s=len(x0) / best,
+                         lattice_updates=lu, mlups=lu / best / 1e6,
+                         converged=int((r.flags == 0).sum()), items=int(r.flags.size),
+                         mean_steps=float(r.steps.mean()))
+    return out
+
+
+def cpu_baseline(kappa, steps):
+    from oracle import oracle as O
+    n = kappa.shape[0]
+    p = O.Params(nx=n, ny=n, tau=0.8, eps=0.4, nu=0.1, walls_y=1)
+    f = O.rest_state(p)
+    t0 = time.perf_counter()
+    O.run(p, kappa, (1e-6, 0.0), f=f, max_steps=steps)
+    dt = time.perf_counter() - t0
+    lu = steps * n * n
+    return dict(value=lu / dt / 1e6, unit="MLUPS", cores=O.num_threads(), kind="oracle",
+                sample=f"{steps} steps of the {n}x{n} workload (FP64 C oracle, OpenMP over rows), "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-local", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 302 MB device copy, the reference for HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1312_0195_amd import inputs as I
+    from paper_1312_0195_amd import lbm as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    L.lib()
+    w = I.workload_fine(seed=1)
+    kappa = w["kappa"]
+    n = kappa.shape[0]
+    cells = n * n
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 9 planes of 2048 x 2048 FP32
+        src = torch.ones(9 * cells, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 4}), flush=True)
+        del src, dst
+    fine = bench_fine(L, torch, kappa, args.steps, args.warmup)
+    ms_per_step = fine["event_ms"] / args.steps
+    mlups = cells * args.steps / (fine["event_ms"] * 1e-3) / 1e6
+    step_ms = fine["step_kernel_ms"]
+    achieved = BYTES_PER_LU * cells / (step_ms * 1e-3) / 1e9
+    traffic = _traffic_per_launch()
+    result = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fine 2048x2048 D2Q9 Brinkman LBM, log-normal K (sigma 1.5, "
+                               "corr 32), tau 0.8, g 1e-6, walls in y, FP32 deviation "
+                               "populations, mean-velocity reduction every 100 steps",
+                   "nx": n, "ny": n, "check_every": 100},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step<float, walls, scalar>",
+                     "avg_launch_us": round(step_ms * 1e3, 3),
+                     "bytes_per_launch": BYTES_PER_LU * cells},
+        "wall_s": round(fine["wall_s"], 3),
+    }
+    if not args.no_local:
+        kd = torch.as_tensor(kappa).cuda()
+        result["local_keff"] = bench_local(L, torch, kd)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(kappa, args.cpu_steps)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

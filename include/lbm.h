@@ -1,0 +1,223 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the upscaled
+ * Brinkman lattice Boltzmann method of J. Li and D. Brown, "Upscaled Lattice
+ * Boltzmann Method for Simulations of Flows in Heterogeneous Porous Media"
+ * (arXiv:1312.0195).
+ *
+ * All quantities are in lattice units (dx = dt = c = 1, c_s^2 = 1/3). The
+ * D2Q9 populations are numbered as in Sec. 2 of the paper:
+ *   0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1).
+ * Fields are row-major [ny][nx] with x fastest.
+ *
+ * Memory ownership: every device buffer passed in is owned by the caller. The
+ * library never allocates or frees device memory; scratch space comes from a
+ * caller-provided workspace whose size the *_workspace_bytes functions
+ * report. An lbm_handle is host memory owned by the library (freed by
+ * lbm_destroy); it only refers to the caller's workspace.
+ *
+ * Streams and synchronisation: work is queued on the hipStream_t given at
+ * set-up. Calls that return values into host memory (steps_done, mean_u)
+ * synchronise that stream before they return; the others are asynchronous.
+ *
+ * Errors: every entry point returns an lbm_status. Parameters are checked on
+ * the host before anything is launched. No exception or abort crosses the
+ * ABI. lbm_last_error() gives a thread-local description of the last failure.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,      /* invalid argument (checked on the host) */
+    LBM_EDEVICE = -2,     /* a HIP call failed */
+    LBM_ENOTCONV = -3,    /* step cap reached before the tolerance */
+    LBM_ENONFINITE = -4,  /* NaN or Inf in the mean velocity */
+    LBM_EWORKSPACE = -5   /* workspace missing, misaligned or too small */
+} lbm_status;
+
+/* Population storage of the fine-grid solver. */
+enum {
+    LBM_F32_SHIFTED = 0, /* FP32 deviations f_a - w_a rho0 (the fast path) */
+    LBM_F64 = 1          /* FP64 deviations (reference-precision runs) */
+};
+
+/* Kind of permeability given per cell. */
+enum {
+    LBM_PERM_SCALAR = 1, /* kappa(x), Eq. f_m-depends-on-u */
+    LBM_PERM_TENSOR = 4  /* [kxx, kxy, kyx, kyy](x), Eq. f_m-depends-on-u-and-tensor-k */
+};
+
+/* Parameters of one lattice (Sec. 2). tau >= 1/2 sets nu_eff = (tau - 1/2)/3;
+ * nu is the viscosity in the drag term, independent of nu_eff (Eq.
+ * Brinkman-like); eps is the porosity; (gx, gy) the uniform body force per
+ * unit mass G, used when no per-cell force field is given. */
+typedef struct {
+    int32_t nx, ny;
+    double tau;
+    double eps;
+    double nu;
+    double rho0;
+    double gx, gy;
+    int32_t walls_y;   /* 0: periodic in y; 1: halfway bounce-back walls half a
+                          cell below row 0 and above row ny-1 (x is periodic) */
+    int32_t pop_dtype; /* LBM_F32_SHIFTED or LBM_F64 */
+    int32_t perm_kind; /* LBM_PERM_SCALAR or LBM_PERM_TENSOR */
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* ---------------------------------------------------------------------------
+ * Fine-grid solver: the time stepping of Sec. 2.2 (Eqs. feq, explicit-u-in-Guo,
+ * final-ueq-of-S-C, f-evolution-of-S-C) on an nx x ny lattice.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of workspace lbm_init needs for these parameters (0 if invalid). */
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/* Set up a solver at the rest state f_a = w_a rho0.
+ *   d_perm  : device FP64, [ny][nx] (scalar) or [ny][nx][4] (tensor), read
+ *             once. Scalars must be > 0 (+inf means no drag); tensors must be
+ *             invertible. Invalid values give LBM_EINVAL.
+ *   d_force : device FP64 [ny][nx][2] per-cell G, or NULL for (gx, gy).
+ *   d_ws    : device workspace of ws_bytes >= lbm_workspace_bytes(p),
+ *             256-byte aligned; it must stay alive until lbm_destroy.
+ * Synchronises the stream (the permeability check is read back). */
+lbm_status lbm_init(lbm_handle **h, const lbm_params *p, const double *d_perm,
+                    const double *d_force, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Advance up to max_steps time steps. With check_every > 0 the volume-averaged
+ * flow velocity (Sec. 3, FP64 reduction) is taken every check_every steps;
+ * with tol > 0 the call returns LBM_OK once the change between two checks is
+ * <= tol times its norm, and LBM_ENOTCONV if max_steps pass first. tol <= 0
+ * runs exactly max_steps. steps_done (may be NULL) gets the steps taken by
+ * this call; mean_u (may be NULL) the mean velocity of the final state.
+ * Synchronises the stream when a check runs or mean_u is requested. */
+lbm_status lbm_step(lbm_handle *h, int64_t max_steps, double tol, int32_t check_every,
+                    int64_t *steps_done, double mean_u[2]);
+
+/* Flow velocity u (Eq. u-of-S-C) and density of the current state.
+ *   d_u   : device FP64 [2][ny][nx] (ux plane, then uy plane)
+ *   d_rho : device FP64 [ny][nx], or NULL. */
+lbm_status lbm_fields(lbm_handle *h, double *d_u, double *d_rho);
+
+/* Full populations f_a (not shifted) of the current state, device FP64
+ * [9][ny][nx], pre-collision at the current time step. */
+lbm_status lbm_get_populations(lbm_handle *h, double *d_f);
+
+/* Replace the state by the populations d_f (same layout as above), e.g. to
+ * resume from a checkpoint. The step counter is left unchanged. */
+lbm_status lbm_set_populations(lbm_handle *h, const double *d_f);
+
+/* Total time steps taken since lbm_init. */
+int64_t lbm_steps_total(const lbm_handle *h);
+
+void lbm_destroy(lbm_handle *h);
+
+/* ---------------------------------------------------------------------------
+ * Batched local problems: effective permeability per subdomain (Sec. 3).
+ * Each patch is a periodic side x side window of the fine permeability field,
+ * run from rest under G1 = (g, 0) and/or G2 = (0, g) until its own mean
+ * velocity converges; then Eq. tensor-kappa gives
+ *   kxx = nu ubar1_x / g, kxy = nu ubar2_x / g, kyx = nu ubar1_y / g,
+ *   kyy = nu ubar2_y / g.
+ * All items of one call run in one persistent launch.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double tau, eps, nu;  /* as in lbm_params */
+    double g;             /* drive magnitude G_const > 0 */
+    double tol;           /* relative change of the mean velocity between checks */
+    int32_t check_every;  /* steps between checks, even and >= 2 */
+    int64_t max_steps;    /* per-item cap (rounded up to a multiple of check_every) */
+} lbm_local_params;
+
+/* One row of the tile table: how items of side `side` are laid out on a
+ * workgroup of block_threads threads. slot_threads threads share one item
+ * (each holding ceil(side^2 / slot_threads) cells, at most 4); a workgroup
+ * runs block_threads / slot_threads items side by side. Items of sides not in
+ * the table use the built-in choice. */
+typedef struct {
+    int32_t side;
+    int32_t slot_threads;
+} lbm_local_tile;
+
+/* Largest patch side the local solver accepts. */
+int32_t lbm_local_max_side(void);
+
+size_t lbm_local_workspace_bytes(int32_t n_patches);
+
+/* h_x0, h_y0, h_side, h_drive_mask: HOST int32 arrays of n_patches entries
+ *   (origin of the window in the field, side in [2, lbm_local_max_side()],
+ *   drive bits: 1 = x drive, 2 = y drive).
+ * d_kappa_field: device FP64 [fny][fnx]; windows wrap periodically.
+ * d_keff : device FP64 [n_patches][4] = kxx, kxy, kyx, kyy (entries of a
+ *          skipped drive are NaN).
+ * d_steps: device int32 [n_patches][2] steps taken per drive (or NULL).
+ * d_flags: device int32 [n_patches][2]: 0 converged, 1 step cap reached,
+ *          2 non-finite, -1 drive skipped (or NULL).
+ * tiles/n_tiles: optional tile table (NULL/0 for the built-in one).
+ * block_threads: workgroup size, 256, 512 or 1024 (0 for 1024).
+ * Asynchronous; the host arrays may be reused when the call returns. */
+lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patches, const int32_t *h_x0,
+                          const int32_t *h_y0, const int32_t *h_side, const int32_t *h_drive_mask,
+                          const double *d_kappa_field, int32_t fnx, int32_t fny, double *d_keff,
+                          int32_t *d_steps, int32_t *d_flags, const lbm_local_tile *tiles,
+                          int32_t n_tiles, int32_t block_threads, void *d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Coarse-grid solve (Sec. 3, Sec. 4.3): the same scheme on the grid coarsened
+ * by r, with the effective permeability per coarse cell. The physical rho0,
+ * nu_eff, eps, nu and G are kept while dx and dt both grow by r, so in
+ * lattice units tau_c = 1/2 + (tau_f - 1/2)/r, nu_c = nu_f / r,
+ * kappa_c = kappa_f / r^2 and G_c = r G_f; velocities are unchanged.
+ * ------------------------------------------------------------------------- */
+
+enum { LBM_KEFF_SCALAR = 0, LBM_KEFF_TENSOR = 1 };
+
+/* Coarse lattice parameters for a fine lattice coarsened by r (the mapping
+ * above; uniform force scaled by r). */
+lbm_status lbm_coarse_params(const lbm_params *fine, int32_t r, lbm_params *coarse);
+
+size_t lbm_coarse_workspace_bytes(int32_t ncx, int32_t ncy);
+
+/* fine     : fine-lattice parameters (nx, ny divisible by r); walls_y must be
+ *            0 (the paper's coarse runs are periodic).
+ * d_keff   : device FP64 [ncy][ncx][4] (kxx, kxy, kyx, kyy) in FINE lattice
+ *            units, as lbm_local_keff returns them.
+ * keff_mode: LBM_KEFF_SCALAR uses (kxx + kyy)/2 per cell (the scalar kappa*
+ *            of Sec. 4.3), LBM_KEFF_TENSOR the full tensor (Eq.
+ *            f_m-depends-on-u-and-tensor-k).
+ * d_force  : device FP64 [ncy][ncx][2] G per coarse cell in FINE lattice
+ *            units, or NULL for (fine->gx, fine->gy).
+ * Runs from rest until the relative L2 change of the velocity field between
+ * checks every check_every coarse steps is <= tol (or max_steps coarse
+ * steps). d_u: device FP64 [2][ncy][ncx]; d_rho: [ncy][ncx] or NULL.
+ * Synchronises the stream (steps_done is returned). */
+lbm_status lbm_coarse_solve(const lbm_params *fine, int32_t r, const double *d_keff,
+                            int32_t keff_mode, const double *d_force, int64_t max_steps,
+                            double tol, int32_t check_every, double *d_u, double *d_rho,
+                            int64_t *steps_done, void *d_ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------- */
+
+const char *lbm_status_str(lbm_status s);
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

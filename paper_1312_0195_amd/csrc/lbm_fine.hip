@@ -1,0 +1,735 @@
+// lbm_fine.hip -- fine-grid solver of liblbm (Sec. 2.2 of the paper).
+//
+// One time step is ONE kernel pass over HBM: every cell pulls its nine
+// incoming post-collision populations from its neighbours (streaming of Eq.
+// f-evolution-of-S-C read backwards), collides them in registers and writes
+// the nine new post-collision values to its own cell in the other buffer.
+// The state in memory is therefore the post-collision populations of the
+// previous step; the pre-collision populations at the current step are the
+// pulled ones, which is what lbm_fields and lbm_get_populations report.
+//
+// Storage: structure of arrays, plane a holds population a for all cells
+// (x fastest), so each of the 9 loads and 9 stores of a wavefront is 64
+// consecutive elements. FP32 planes store deviations f_a - w_a rho0 from the
+// rest state: the velocity signal is ~1e-5 of a population, and storing the
+// deviations keeps FP32 rounding relative to the signal, not to w_a rho0.
+//
+// Collision in deviation form, with dr = sum f~, j = sum e f~, rho = rho0 + dr:
+//   rho u    = D (j + eps rho G / 2)                  Eq. explicit-u-in-Guo
+//   rho u_eq = 2 tau rho u + (1 - 2 tau) j            Eq. final-ueq-of-S-C
+//   f~eq_a   = w_a (dr + 3 e_a . rho u_eq)            Eq. feq minus w_a rho0
+//   f~*_a    = f~_a + (f~eq_a - f~_a) / tau           Eq. f-evolution-of-S-C
+// with D = 1 / (1 + eps nu / (2 kappa)) per cell, or, for a tensor
+// permeability K, rho u = (K + eps nu I / 2)^{-1} K (j + eps rho G / 2) (Eq.
+// u-of-S-C with Eq. f_m-depends-on-u-and-tensor-k). No division is needed in
+// the step. The algebra is exact; only the rounding order differs from a
+// literal transcription. The collision arithmetic is FP64 for both storage
+// types; FP32 storage only rounds the nine values written per cell.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename R>
+struct StepArgs {
+    const R *__restrict__ fin;
+    R *__restrict__ fout;
+    const R *__restrict__ coef;    // perm_kind planes of cstride elements
+    const R *__restrict__ hforce;  // 2 planes: eps G / 2 per cell (or null)
+    int nx, ny;
+    int stride;   // plane stride of the populations, elements
+    int cstride;  // plane stride of coef / hforce, elements
+    R om;         // 1 / tau
+    R omc;        // 1 - 1 / tau
+    R twotau;     // 2 tau
+    R omtt;       // 1 - 2 tau
+    R hegx, hegy; // eps G / 2 for a uniform force
+    R rho0;
+    // FP64 copies of the constants for the FP64 arithmetic
+    double hegx_d, hegy_d, om_d, omc_d, twotau_d, omtt_d, rho0_d;
+};
+
+// Pull the nine pre-collision deviations of cell (x, y): f_a(x) = f*_a(x - e_a)
+// from the previous step, with periodic wrap in x (and in y without walls)
+// and halfway bounce-back f_a(x) = f*_opp(a)(x) where x - e_a is beyond a wall.
+template <typename R, bool WALLS>
+__device__ __forceinline__ void pull(const R *__restrict__ fin, int stride, int nx, int ny, int x,
+                                     int y, R f[9])
+{
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const int rc = y * nx;
+    const R *p0 = fin;
+    const R *p1 = fin + stride;
+    const R *p2 = fin + 2 * (size_t)stride;
+    const R *p3 = fin + 3 * (size_t)stride;
+    const R *p4 = fin + 4 * (size_t)stride;
+    const R *p5 = fin + 5 * (size_t)stride;
+    const R *p6 = fin + 6 * (size_t)stride;
+    const R *p7 = fin + 7 * (size_t)stride;
+    const R *p8 = fin + 8 * (size_t)stride;
+    f[0] = p0[rc + x];
+    f[1] = p1[rc + xm];
+    f[3] = p3[rc + xp];
+    if (WALLS) {
+        const bool lo = (y == 0), hi = (y == ny - 1);
+        const int rm = (lo ? y : y - 1) * nx;
+        const int rp = (hi ? y : y + 1) * nx;
+        f[2] = lo ? p4[rc + x] : p2[rm + x];
+        f[5] = lo ? p7[rc + x] : p5[rm + xm];
+        f[6] = lo ? p8[rc + x] : p6[rm + xp];
+        f[4] = hi ? p2[rc + x] : p4[rp + x];
+        f[7] = hi ? p5[rc + x] : p7[rp + xp];
+        f[8] = hi ? p6[rc + x] : p8[rp + xm];
+    } else {
+        const int rm = ((y == 0) ? ny - 1 : y - 1) * nx;
+        const int rp = ((y == ny - 1) ? 0 : y + 1) * nx;
+        f[2] = p2[rm + x];
+        f[5] = p5[rm + xm];
+        f[6] = p6[rm + xp];
+        f[4] = p4[rp + x];
+        f[7] = p7[rp + xp];
+        f[8] = p8[rp + xm];
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void moments(const R f[9], R &dr, R &jx, R &jy)
+{
+    dr = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+    jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+}
+
+template <typename R, bool WALLS, int PK, bool FF>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
+{
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= a.nx) return;
+    R fr[9];
+    pull<R, WALLS>(a.fin, a.stride, a.nx, a.ny, x, y, fr);
+    const int c = y * a.nx + x;
+    // The arithmetic runs in FP64 whatever the storage type: with FP32 storage
+    // the rounding of the collision itself (not of the stored values) is what
+    // limits accuracy, and FP64 VALU work is hidden under the HBM traffic.
+    double f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = (double)fr[i];
+    double dr, jx, jy;
+    moments(f, dr, jx, jy);
+    const double rho = a.rho0_d + dr;
+    double hx, hy;
+    if (FF) {
+        hx = jx + (double)a.hforce[c] * rho;
+        hy = jy + (double)a.hforce[a.cstride + c] * rho;
+    } else {
+        hx = jx + a.hegx_d * rho;
+        hy = jy + a.hegy_d * rho;
+    }
+    double mx, my;  // rho u_eq
+    if (PK == 1) {
+        const double tD = a.twotau_d * (double)a.coef[c];
+        mx = tD * hx + a.omtt_d * jx;
+        my = tD * hy + a.omtt_d * jy;
+    } else {
+        const double m00 = a.coef[c], m01 = a.coef[a.cstride + c];
+        const double m10 = a.coef[2 * a.cstride + c], m11 = a.coef[3 * a.cstride + c];
+        mx = a.twotau_d * (m00 * hx + m01 * hy) + a.omtt_d * jx;
+        my = a.twotau_d * (m10 * hx + m11 * hy) + a.omtt_d * jy;
+    }
+    const double om = a.om_d, omc = a.omc_d;
+    const double s0 = (4.0 / 9.0) * om * dr;
+    const double b = (1.0 / 9.0) * om * dr;
+    const double bx = (1.0 / 3.0) * om * mx;
+    const double by = (1.0 / 3.0) * om * my;
+    const double cc = (1.0 / 36.0) * om * dr;
+    const double cx = (1.0 / 12.0) * om * mx;
+    const double cy = (1.0 / 12.0) * om * my;
+    const double pp = cx + cy, qq = cx - cy;
+    R *o = a.fout;
+    const size_t S = (size_t)a.stride;
+    o[c] = (R)(omc * f[0] + s0);
+    o[S + c] = (R)(omc * f[1] + (b + bx));
+    o[2 * S + c] = (R)(omc * f[2] + (b + by));
+    o[3 * S + c] = (R)(omc * f[3] + (b - bx));
+    o[4 * S + c] = (R)(omc * f[4] + (b - by));
+    o[5 * S + c] = (R)(omc * f[5] + (cc + pp));
+    o[6 * S + c] = (R)(omc * f[6] + (cc - qq));
+    o[7 * S + c] = (R)(omc * f[7] + (cc - pp));
+    o[8 * S + c] = (R)(omc * f[8] + (cc + qq));
+}
+
+// Flow velocity (Eq. u-of-S-C) and density of the current state in FP64, and
+// per-block FP64 partial sums of u for the volume average.
+template <typename R, bool WALLS, int PK, bool FF>
+__global__ __launch_bounds__(kBlock) void k_fields(StepArgs<R> a, double *__restrict__ u_out,
+                                                   double *__restrict__ rho_out,
+                                                   double *__restrict__ partials)
+{
+    __shared__ double red[2][kBlock / 64];
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    const int y = blockIdx.y;
+    double ux = 0.0, uy = 0.0;
+    if (x < a.nx) {
+        R fr[9];
+        pull<R, WALLS>(a.fin, a.stride, a.nx, a.ny, x, y, fr);
+        double f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = (double)fr[i];
+        double dr, jx, jy;
+        moments(f, dr, jx, jy);
+        const double rho = a.rho0_d + dr;
+        const int c = y * a.nx + x;
+        double hx, hy;
+        if (FF) {
+            hx = jx + (double)a.hforce[c] * rho;
+            hy = jy + (double)a.hforce[a.cstride + c] * rho;
+        } else {
+            hx = jx + a.hegx_d * rho;
+            hy = jy + a.hegy_d * rho;
+        }
+        if (PK == 1) {
+            const double D = (double)a.coef[c];
+            ux = D * hx / rho;
+            uy = D * hy / rho;
+        } else {
+            const double m00 = a.coef[c], m01 = a.coef[a.cstride + c];
+            const double m10 = a.coef[2 * a.cstride + c], m11 = a.coef[3 * a.cstride + c];
+            ux = (m00 * hx + m01 * hy) / rho;
+            uy = (m10 * hx + m11 * hy) / rho;
+        }
+        if (u_out) {
+            const size_t N = (size_t)a.nx * a.ny;
+            u_out[c] = ux;
+            u_out[N + c] = uy;
+        }
+        if (rho_out) rho_out[c] = rho;
+    }
+    if (partials) {
+        ux = wave_sum(ux);
+        uy = wave_sum(uy);
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[0][wv] = ux;
+            red[1][wv] = uy;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sx = 0.0, sy = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                sx += red[0][w];
+                sy += red[1][w];
+            }
+            const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+            partials[2 * bid] = sx;
+            partials[2 * bid + 1] = sy;
+        }
+    }
+}
+
+// Fixed-order sum of n (x, y) pairs into out[0..1], divided by ncells.
+__global__ __launch_bounds__(kBlock) void k_reduce_pairs(const double *__restrict__ partials,
+                                                         int n, double inv_cells,
+                                                         double *__restrict__ out)
+{
+    __shared__ double red[2][kBlock / 64];
+    double sx = 0.0, sy = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        sx += partials[2 * i];
+        sy += partials[2 * i + 1];
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wv] = sx;
+        red[1][wv] = sy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tx = 0.0, ty = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            tx += red[0][w];
+            ty += red[1][w];
+        }
+        out[0] = tx * inv_cells;
+        out[1] = ty * inv_cells;
+    }
+}
+
+__global__ void k_zero_i32(int *__restrict__ p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// Per-cell coefficient from the permeability (FP64, rounded once to R),
+// eps G / 2 per cell, and the rest state (zero deviations) in buffer fin.
+template <typename R, int PK>
+__global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ perm,
+                                                 const double *__restrict__ force, int n,
+                                                 double eps, double nu, R *__restrict__ coef,
+                                                 R *__restrict__ hforce, int cstride,
+                                                 R *__restrict__ pops, int stride,
+                                                 int *__restrict__ bad)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    const double h = 0.5 * eps * nu;
+    if (PK == 1) {
+        const double k = perm[c];
+        if (!(k > 0.0)) atomicOr(bad, 1);  // also catches NaN
+        // D = 1 / (1 + eps nu / (2 kappa)); kappa = +inf gives 1
+        coef[c] = (R)(1.0 / (1.0 + h / k));
+    } else {
+        const double kxx = perm[4 * c], kxy = perm[4 * c + 1];
+        const double kyx = perm[4 * c + 2], kyy = perm[4 * c + 3];
+        const double det = kxx * kyy - kxy * kyx;
+        // M = (K + h I)^{-1} K
+        const double axx = kxx + h, axy = kxy, ayx = kyx, ayy = kyy + h;
+        const double adet = axx * ayy - axy * ayx;
+        const bool ok = std::isfinite(det) && det != 0.0 && std::isfinite(adet) && adet != 0.0;
+        if (!ok) atomicOr(bad, 1);
+        const double ia = 1.0 / adet;
+        coef[c] = (R)(ia * (ayy * kxx - axy * kyx));
+        coef[cstride + c] = (R)(ia * (ayy * kxy - axy * kyy));
+        coef[2 * cstride + c] = (R)(ia * (-ayx * kxx + axx * kyx));
+        coef[3 * cstride + c] = (R)(ia * (-ayx * kxy + axx * kyy));
+    }
+    if (force) {
+        const double gx = force[2 * c], gy = force[2 * c + 1];
+        if (!std::isfinite(gx) || !std::isfinite(gy)) atomicOr(bad, 2);
+        hforce[c] = (R)(0.5 * eps * gx);
+        hforce[cstride + c] = (R)(0.5 * eps * gy);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) pops[(size_t)q * stride + c] = (R)0;
+}
+
+// Full pre-collision populations of the current state, FP64 [9][ny][nx].
+template <typename R, bool WALLS>
+__global__ __launch_bounds__(kBlock) void k_get_pops(const R *__restrict__ fin, int stride, int nx,
+                                                     int ny, double rho0, double *__restrict__ out)
+{
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= nx) return;
+    R f[9];
+    pull<R, WALLS>(fin, stride, nx, ny, x, y, f);
+    const size_t N = (size_t)nx * ny;
+    const int c = y * nx + x;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q * N + c] = (double)f[q] + weight(q) * rho0;
+}
+
+// Inverse of the pull: store g with pull(g) = f, i.e. g_b(x) = f_b(x + e_b),
+// or f_opp(b)(x) when x + e_b lies beyond a wall.
+template <typename R, bool WALLS>
+__global__ __launch_bounds__(kBlock) void k_set_pops(const double *__restrict__ in, int nx, int ny,
+                                                     double rho0, R *__restrict__ fout, int stride)
+{
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= nx) return;
+    const size_t N = (size_t)nx * ny;
+    const int c = y * nx + x;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        int xs = x + ex(b);
+        int ys = y + ey(b);
+        xs = (xs < 0) ? nx - 1 : (xs >= nx ? 0 : xs);
+        int src_pop = b;
+        if (ys < 0 || ys >= ny) {
+            if (WALLS) {
+                xs = x;
+                ys = y;
+                src_pop = opposite(b);
+            } else {
+                ys = (ys < 0) ? ny - 1 : 0;
+            }
+        }
+        const double v = in[src_pop * N + (size_t)ys * nx + xs] - weight(src_pop) * rho0;
+        fout[(size_t)b * stride + c] = (R)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct Layout {
+    size_t elem;      // bytes per population element
+    size_t stride;    // elements per population plane
+    size_t cstride;   // elements per coefficient plane
+    size_t off_a, off_b, off_coef, off_force, off_part, off_res, off_flag, total;
+    int nbx, nby;     // launch grid of the per-cell kernels
+};
+
+bool params_ok(const lbm_params *p, std::string &why)
+{
+    if (!p) { why = "params is NULL"; return false; }
+    if (p->nx < 1 || p->ny < 1) { why = "nx and ny must be >= 1"; return false; }
+    if ((int64_t)p->nx * p->ny * 9 >= (int64_t)1 << 31) { why = "grid too large (9 nx ny must be < 2^31)"; return false; }
+    if (!(p->tau >= 0.5) || !std::isfinite(p->tau)) { why = "tau must be finite and >= 0.5"; return false; }
+    if (!(p->eps > 0.0 && p->eps <= 1.0)) { why = "eps must lie in (0, 1]"; return false; }
+    if (!(p->nu > 0.0) || !std::isfinite(p->nu)) { why = "nu must be finite and > 0"; return false; }
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) { why = "rho0 must be finite and > 0"; return false; }
+    if (!std::isfinite(p->gx) || !std::isfinite(p->gy)) { why = "gx, gy must be finite"; return false; }
+    if (p->walls_y != 0 && p->walls_y != 1) { why = "walls_y must be 0 or 1"; return false; }
+    if (p->pop_dtype != LBM_F32_SHIFTED && p->pop_dtype != LBM_F64) { why = "unknown pop_dtype"; return false; }
+    if (p->perm_kind != LBM_PERM_SCALAR && p->perm_kind != LBM_PERM_TENSOR) { why = "perm_kind must be 1 or 4"; return false; }
+    return true;
+}
+
+Layout layout_of(const lbm_params *p)
+{
+    Layout L{};
+    const size_t n = (size_t)p->nx * p->ny;
+    L.elem = (p->pop_dtype == LBM_F64) ? 8 : 4;
+    L.stride = align_up(n, 64);
+    L.cstride = n;
+    size_t off = 0;
+    L.off_a = off;  off = align_up(off + 9 * L.stride * L.elem);
+    L.off_b = off;  off = align_up(off + 9 * L.stride * L.elem);
+    L.off_coef = off; off = align_up(off + (size_t)p->perm_kind * L.cstride * L.elem);
+    L.off_force = off; off = align_up(off + 2 * L.cstride * L.elem);
+    L.nbx = (p->nx + kBlock - 1) / kBlock;
+    L.nby = p->ny;
+    L.off_part = off; off = align_up(off + 2 * sizeof(double) * (size_t)L.nbx * L.nby);
+    L.off_res = off;  off = align_up(off + 4 * sizeof(double));
+    L.off_flag = off; off = align_up(off + sizeof(int));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+}  // namespace lbm
+
+struct lbm_handle {
+    lbm_params p;
+    lbm::Layout L;
+    hipStream_t stream;
+    char *ws;
+    int cur;            // 0: state in buffer A, 1: in buffer B
+    bool has_force;
+    int64_t steps_total;
+    double prev_u[2];
+    bool have_prev;
+    double *host_res;   // pinned host copy of the reduction result
+};
+
+namespace lbm {
+namespace {
+
+template <typename R>
+StepArgs<R> step_args(const lbm_handle *h)
+{
+    StepArgs<R> a{};
+    const Layout &L = h->L;
+    a.fin = reinterpret_cast<const R *>(h->ws + (h->cur ? L.off_b : L.off_a));
+    a.fout = reinterpret_cast<R *>(h->ws + (h->cur ? L.off_a : L.off_b));
+    a.coef = reinterpret_cast<const R *>(h->ws + L.off_coef);
+    a.hforce = h->has_force ? reinterpret_cast<const R *>(h->ws + L.off_force) : nullptr;
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.stride = (int)L.stride;
+    a.cstride = (int)L.cstride;
+    const double tau = h->p.tau;
+    a.om = (R)(1.0 / tau);
+    a.omc = (R)(1.0 - 1.0 / tau);
+    a.twotau = (R)(2.0 * tau);
+    a.omtt = (R)(1.0 - 2.0 * tau);
+    a.hegx = (R)(0.5 * h->p.eps * h->p.gx);
+    a.hegy = (R)(0.5 * h->p.eps * h->p.gy);
+    a.rho0 = (R)h->p.rho0;
+    a.hegx_d = 0.5 * h->p.eps * h->p.gx;
+    a.hegy_d = 0.5 * h->p.eps * h->p.gy;
+    a.om_d = 1.0 / tau;
+    a.omc_d = 1.0 - 1.0 / tau;
+    a.twotau_d = 2.0 * tau;
+    a.omtt_d = 1.0 - 2.0 * tau;
+    a.rho0_d = h->p.rho0;
+    return a;
+}
+
+template <typename R, bool W, int PK, bool FF>
+void launch_step_t(const lbm_handle *h)
+{
+    const dim3 grid(h->L.nbx, h->L.nby);
+    hipLaunchKernelGGL((k_step<R, W, PK, FF>), grid, dim3(kBlock), 0, h->stream, step_args<R>(h));
+}
+
+template <typename R, bool W, int PK, bool FF>
+void launch_fields_t(const lbm_handle *h, double *u, double *rho, double *part)
+{
+    const dim3 grid(h->L.nbx, h->L.nby);
+    hipLaunchKernelGGL((k_fields<R, W, PK, FF>), grid, dim3(kBlock), 0, h->stream, step_args<R>(h),
+                       u, rho, part);
+}
+
+// Dispatch on (dtype, walls, perm kind, force field) to one instantiation.
+template <template <typename, bool, int, bool> class Fn, typename... Args>
+void dispatch(const lbm_handle *h, Args... args)
+{
+    const bool w = h->p.walls_y != 0, ff = h->has_force, t = h->p.perm_kind == LBM_PERM_TENSOR;
+#define LBM_CASE(R, W, PK, FF) \
+    if (w == W && t == (PK == 4) && ff == FF) { Fn<R, W, PK, FF>::run(h, args...); return; }
+    if (h->p.pop_dtype == LBM_F64) {
+        LBM_CASE(double, false, 1, false) LBM_CASE(double, false, 1, true)
+        LBM_CASE(double, false, 4, false) LBM_CASE(double, false, 4, true)
+        LBM_CASE(double, true, 1, false)  LBM_CASE(double, true, 1, true)
+        LBM_CASE(double, true, 4, false)  LBM_CASE(double, true, 4, true)
+    } else {
+        LBM_CASE(float, false, 1, false) LBM_CASE(float, false, 1, true)
+        LBM_CASE(float, false, 4, false) LBM_CASE(float, false, 4, true)
+        LBM_CASE(float, true, 1, false)  LBM_CASE(float, true, 1, true)
+        LBM_CASE(float, true, 4, false)  LBM_CASE(float, true, 4, true)
+    }
+#undef LBM_CASE
+}
+
+template <typename R, bool W, int PK, bool FF>
+struct StepFn {
+    static void run(const lbm_handle *h) { launch_step_t<R, W, PK, FF>(h); }
+};
+template <typename R, bool W, int PK, bool FF>
+struct FieldsFn {
+    static void run(const lbm_handle *h, double *u, double *rho, double *part)
+    {
+        launch_fields_t<R, W, PK, FF>(h, u, rho, part);
+    }
+};
+
+lbm_status mean_velocity(lbm_handle *h, double out[2])
+{
+    double *part = reinterpret_cast<double *>(h->ws + h->L.off_part);
+    double *res = reinterpret_cast<double *>(h->ws + h->L.off_res);
+    dispatch<FieldsFn>(h, (double *)nullptr, (double *)nullptr, part);
+    const int nparts = h->L.nbx * h->L.nby;
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlock), 0, h->stream, part, nparts,
+                       1.0 / ((double)h->p.nx * h->p.ny), res);
+    LBM_HIP(hipGetLastError());
+    LBM_HIP(hipMemcpyAsync(h->host_res, res, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LBM_HIP(hipStreamSynchronize(h->stream));
+    out[0] = h->host_res[0];
+    out[1] = h->host_res[1];
+    return LBM_OK;
+}
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" size_t lbm_workspace_bytes(const lbm_params *p)
+{
+    std::string why;
+    if (!params_ok(p, why)) return 0;
+    return layout_of(p).total;
+}
+
+extern "C" lbm_status lbm_init(lbm_handle **out, const lbm_params *p, const double *d_perm,
+                               const double *d_force, void *d_ws, size_t ws_bytes,
+                               hipStream_t stream)
+{
+    if (!out) return set_error(LBM_EINVAL, "lbm_init: handle pointer is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!params_ok(p, why)) return set_error(LBM_EINVAL, "lbm_init: " + why);
+    if (!d_perm) return set_error(LBM_EINVAL, "lbm_init: permeability pointer is NULL");
+    const Layout L = layout_of(p);
+    if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0)
+        return set_error(LBM_EWORKSPACE, "lbm_init: workspace is NULL or not 256-byte aligned");
+    if (ws_bytes < L.total)
+        return set_error(LBM_EWORKSPACE, "lbm_init: workspace too small (need " +
+                                             std::to_string(L.total) + " bytes)");
+    lbm_handle *h = new (std::nothrow) lbm_handle{};
+    if (!h) return set_error(LBM_EINVAL, "lbm_init: out of host memory");
+    h->p = *p;
+    h->L = L;
+    h->stream = stream;
+    h->ws = static_cast<char *>(d_ws);
+    h->cur = 0;
+    h->has_force = d_force != nullptr;
+    if (hipHostMalloc((void **)&h->host_res, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return set_error(LBM_EDEVICE, "lbm_init: hipHostMalloc failed");
+    }
+    int *flag = reinterpret_cast<int *>(h->ws + L.off_flag);
+    const int n = p->nx * p->ny;
+    const int nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, flag, 1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        if (p->pop_dtype == LBM_F64) {
+            double *coef = reinterpret_cast<double *>(h->ws + L.off_coef);
+            double *hf = reinterpret_cast<double *>(h->ws + L.off_force);
+            double *pa = reinterpret_cast<double *>(h->ws + L.off_a);
+            if (p->perm_kind == LBM_PERM_SCALAR)
+                hipLaunchKernelGGL((k_init<double, 1>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
+                                   p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
+            else
+                hipLaunchKernelGGL((k_init<double, 4>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
+                                   p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
+        } else {
+            float *coef = reinterpret_cast<float *>(h->ws + L.off_coef);
+            float *hf = reinterpret_cast<float *>(h->ws + L.off_force);
+            float *pa = reinterpret_cast<float *>(h->ws + L.off_a);
+            if (p->perm_kind == LBM_PERM_SCALAR)
+                hipLaunchKernelGGL((k_init<float, 1>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
+                                   p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
+            else
+                hipLaunchKernelGGL((k_init<float, 4>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
+                                   p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
+        }
+        e = hipGetLastError();
+    }
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipHostFree(h->host_res);
+        delete h;
+        return hip_check(e, "lbm_init");
+    }
+    if (bad) {
+        (void)hipHostFree(h->host_res);
+        delete h;
+        return set_error(LBM_EINVAL, (bad & 1) ? "lbm_init: permeability must be > 0 (or +inf) and "
+                                                 "tensors invertible"
+                                               : "lbm_init: force field has non-finite values");
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_handle *h, int64_t max_steps, double tol, int32_t check_every,
+                               int64_t *steps_done, double mean_u[2])
+{
+    if (!h) return set_error(LBM_EINVAL, "lbm_step: handle is NULL");
+    if (max_steps < 0) return set_error(LBM_EINVAL, "lbm_step: max_steps must be >= 0");
+    if (check_every < 0) return set_error(LBM_EINVAL, "lbm_step: check_every must be >= 0");
+    if (tol > 0.0 && check_every == 0)
+        return set_error(LBM_EINVAL, "lbm_step: a tolerance needs check_every > 0");
+    if (steps_done) *steps_done = 0;
+    lbm_status st = (tol > 0.0) ? LBM_ENOTCONV : LBM_OK;
+    int64_t done = 0;
+    bool last_checked = false;
+    double u[2] = {0.0, 0.0};
+    while (done < max_steps) {
+        dispatch<StepFn>(h);
+        h->cur ^= 1;
+        ++done;
+        ++h->steps_total;
+        last_checked = false;
+        if (check_every > 0 && done % check_every == 0) {
+            LBM_HIP(hipGetLastError());
+            lbm_status s = mean_velocity(h, u);
+            if (s != LBM_OK) return s;
+            last_checked = true;
+            if (!std::isfinite(u[0]) || !std::isfinite(u[1])) {
+                st = LBM_ENONFINITE;
+                break;
+            }
+            if (tol > 0.0 && h->have_prev) {
+                const double dx = u[0] - h->prev_u[0], dy = u[1] - h->prev_u[1];
+                if (std::sqrt(dx * dx + dy * dy) <= tol * std::sqrt(u[0] * u[0] + u[1] * u[1])) {
+                    h->prev_u[0] = u[0];
+                    h->prev_u[1] = u[1];
+                    st = LBM_OK;
+                    break;
+                }
+            }
+            h->prev_u[0] = u[0];
+            h->prev_u[1] = u[1];
+            h->have_prev = true;
+        }
+    }
+    LBM_HIP(hipGetLastError());
+    if (steps_done) *steps_done = done;
+    if (mean_u) {
+        if (!last_checked) {
+            lbm_status s = mean_velocity(h, u);
+            if (s != LBM_OK) return s;
+        }
+        mean_u[0] = u[0];
+        mean_u[1] = u[1];
+        if (st == LBM_OK && (!std::isfinite(u[0]) || !std::isfinite(u[1]))) st = LBM_ENONFINITE;
+    }
+    if (st == LBM_ENOTCONV) return set_error(st, "lbm_step: tolerance not reached within max_steps");
+    if (st == LBM_ENONFINITE) return set_error(st, "lbm_step: non-finite mean velocity");
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_fields(lbm_handle *h, double *d_u, double *d_rho)
+{
+    if (!h) return set_error(LBM_EINVAL, "lbm_fields: handle is NULL");
+    if (!d_u && !d_rho) return set_error(LBM_EINVAL, "lbm_fields: no output given");
+    if (d_u) {
+        dispatch<FieldsFn>(h, d_u, d_rho, (double *)nullptr);
+    } else {
+        // density only: velocities are still computed, into nowhere
+        dispatch<FieldsFn>(h, (double *)nullptr, d_rho, (double *)nullptr);
+    }
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_populations(lbm_handle *h, double *d_f)
+{
+    if (!h || !d_f) return set_error(LBM_EINVAL, "lbm_get_populations: NULL argument");
+    const dim3 grid(h->L.nbx, h->L.nby);
+    const char *cur = h->ws + (h->cur ? h->L.off_b : h->L.off_a);
+    const int S = (int)h->L.stride;
+    const bool w = h->p.walls_y != 0;
+    if (h->p.pop_dtype == LBM_F64) {
+        auto *fin = reinterpret_cast<const double *>(cur);
+        if (w) hipLaunchKernelGGL((k_get_pops<double, true>), grid, dim3(kBlock), 0, h->stream, fin, S, h->p.nx, h->p.ny, h->p.rho0, d_f);
+        else   hipLaunchKernelGGL((k_get_pops<double, false>), grid, dim3(kBlock), 0, h->stream, fin, S, h->p.nx, h->p.ny, h->p.rho0, d_f);
+    } else {
+        auto *fin = reinterpret_cast<const float *>(cur);
+        if (w) hipLaunchKernelGGL((k_get_pops<float, true>), grid, dim3(kBlock), 0, h->stream, fin, S, h->p.nx, h->p.ny, h->p.rho0, d_f);
+        else   hipLaunchKernelGGL((k_get_pops<float, false>), grid, dim3(kBlock), 0, h->stream, fin, S, h->p.nx, h->p.ny, h->p.rho0, d_f);
+    }
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_populations(lbm_handle *h, const double *d_f)
+{
+    if (!h || !d_f) return set_error(LBM_EINVAL, "lbm_set_populations: NULL argument");
+    const dim3 grid(h->L.nbx, h->L.nby);
+    char *cur = h->ws + (h->cur ? h->L.off_b : h->L.off_a);
+    const int S = (int)h->L.stride;
+    const bool w = h->p.walls_y != 0;
+    if (h->p.pop_dtype == LBM_F64) {
+        auto *fo = reinterpret_cast<double *>(cur);
+        if (w) hipLaunchKernelGGL((k_set_pops<double, true>), grid, dim3(kBlock), 0, h->stream, d_f, h->p.nx, h->p.ny, h->p.rho0, fo, S);
+        else   hipLaunchKernelGGL((k_set_pops<double, false>), grid, dim3(kBlock), 0, h->stream, d_f, h->p.nx, h->p.ny, h->p.rho0, fo, S);
+    } else {
+        auto *fo = reinterpret_cast<float *>(cur);
+        if (w) hipLaunchKernelGGL((k_set_pops<float, true>), grid, dim3(kBlock), 0, h->stream, d_f, h->p.nx, h->p.ny, h->p.rho0, fo, S);
+        else   hipLaunchKernelGGL((k_set_pops<float, false>), grid, dim3(kBlock), 0, h->stream, d_f, h->p.nx, h->p.ny, h->p.rho0, fo, S);
+    }
+    h->have_prev = false;
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int64_t lbm_steps_total(const lbm_handle *h) { return h ? h->steps_total : -1; }
+
+extern "C" void lbm_destroy(lbm_handle *h)
+{
+    if (!h) return;
+    if (h->host_res) (void)hipHostFree(h->host_res);
+    delete h;
+}

@@ -1,0 +1,536 @@
+// lbm_local.hip -- batched local problems of Sec. 3 in one persistent launch.
+//
+// Work item = (patch, drive). A patch is a periodic side x side window of the
+// fine permeability field; the drive is G1 = (g, 0) or G2 = (0, g). Each item
+// runs the time stepping of Sec. 2.2 from rest until its own volume-averaged
+// velocity converges, then writes its column of Eq. tensor-kappa:
+//   drive x: kxx = nu ubar_x / g, kyx = nu ubar_y / g
+//   drive y: kxy = nu ubar_x / g, kyy = nu ubar_y / g.
+//
+// On-chip design (gfx950: 160 KB LDS per CU, wave64):
+//  * A workgroup of T threads is split into slots of G threads; each slot
+//    runs one item. Items of one side share a launch-wide tile choice (G per
+//    side) and run side by side, so small patches still fill the CU.
+//  * Populations 1..8 of an item live in LDS (8 planes of side^2 FP32
+//    deviations, 32 B per cell); the rest population and the drag coefficient
+//    stay in registers of the thread that owns the cell.
+//  * Streaming in place ("AA" order): on even steps a cell reads its own
+//    slots and writes the post-collision values back reversed
+//    (A[opp(a)][x] = f*_a); on odd steps it reads f_a from A[opp(a)][x - e_a]
+//    and writes f*_a to A[a][x + e_a]. In both cases the slots a cell reads are
+//    exactly the slots it writes, and different cells own disjoint slots, so a
+//    step needs no barrier between its reads and writes: one workgroup barrier
+//    per step, and a single LDS copy of the state.
+//  * Every check_every steps (even, so the state is back in even order) each
+//    slot sums u (Eq. u-of-S-C) over its cells in FP64: wavefront shuffles,
+//    then the wave partials of the slot in a fixed order. The relative change
+//    of the mean against the previous check decides convergence.
+//  * Items are taken from per-side queues (largest side first) with a global
+//    atomic counter; a slot whose item finished takes the next one. When a
+//    side's queue is empty and all slots are idle the workgroup moves on to
+//    the next side. Every item runs at most max_steps steps, so every
+//    workgroup reaches the end of the queues and exits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kMaxSide = 64;
+constexpr int kMaxClasses = kMaxSide;  // one class per distinct side
+constexpr int kCPT = 4;                // max cells per thread
+
+struct ClassDesc {
+    int side;
+    int slot_threads;  // G
+    int nslots;        // slots in use: T / G (capped by LDS)
+    int cells_per_thread;
+    int begin, count;  // item range in the sorted item list
+};
+
+struct LocalArgs {
+    const int4 *__restrict__ items;      // {x0, y0, side, out = patch * 2 + drive}
+    const ClassDesc *__restrict__ classes;
+    int nclasses;
+    int *__restrict__ counters;          // one per class
+    const double *__restrict__ field;
+    int fnx, fny;
+    double *__restrict__ keff;
+    int *__restrict__ steps_out;
+    int *__restrict__ flags_out;
+    float om, omc, twotau, omtt;         // 1/tau, 1 - 1/tau, 2 tau, 1 - 2 tau
+    float heg;                           // eps g / 2
+    double heg_d;
+    double h;                            // eps nu / 2
+    double nu_over_g;
+    double tol;
+    int check_every;
+    int max_steps;
+};
+
+__device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// One collision of a cell in deviation form (see lbm_fine.hip for the
+// derivation): f[0..8] in, post-collision values out in f.
+__device__ __forceinline__ void collide(float f[9], float D, float hegx, float hegy, const LocalArgs &a)
+{
+    const float dr = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const float jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+    const float jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    const float rho = 1.0f + dr;
+    const float tD = a.twotau * D;
+    const float mx = tD * (jx + hegx * rho) + a.omtt * jx;
+    const float my = tD * (jy + hegy * rho) + a.omtt * jy;
+    const float om = a.om, omc = a.omc;
+    const float s0 = (4.0f / 9.0f) * om * dr;
+    const float b = (1.0f / 9.0f) * om * dr;
+    const float bx = (1.0f / 3.0f) * om * mx;
+    const float by = (1.0f / 3.0f) * om * my;
+    const float cc = (1.0f / 36.0f) * om * dr;
+    const float cx = (1.0f / 12.0f) * om * mx;
+    const float cy = (1.0f / 12.0f) * om * my;
+    const float pp = cx + cy, qq = cx - cy;
+    f[0] = omc * f[0] + s0;
+    f[1] = omc * f[1] + (b + bx);
+    f[2] = omc * f[2] + (b + by);
+    f[3] = omc * f[3] + (b - bx);
+    f[4] = omc * f[4] + (b - by);
+    f[5] = omc * f[5] + (cc + pp);
+    f[6] = omc * f[6] + (cc - qq);
+    f[7] = omc * f[7] + (cc - pp);
+    f[8] = omc * f[8] + (cc + qq);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_local(LocalArgs a)
+{
+    extern __shared__ float lds[];
+    constexpr int NW = T / 64;
+    __shared__ double red[NW][2];
+    __shared__ int ctrl[NW];  // item index per slot (at most NW slots), -1 = none
+
+    const int tid = threadIdx.x;
+    int cls = 0;
+
+    // per-slot state (uniform over the threads of a slot)
+    int item = -1;
+    int steps = 0;
+    bool have_prev = false;
+    double prev_x = 0.0, prev_y = 0.0;
+    int out = 0, x0 = 0, y0 = 0;
+    float hegx = 0.0f, hegy = 0.0f;
+    double hegx_d = 0.0, hegy_d = 0.0;
+    // per-cell registers
+    float f0[kCPT], Dc[kCPT];
+    int xy[kCPT];
+
+    bool need_item = true;
+    __syncthreads();
+
+    while (true) {
+        const ClassDesc cd = a.classes[cls];
+        const int S = cd.side, G = cd.slot_threads, C = cd.cells_per_thread;
+        const int S2 = S * S;
+        const int slot = tid / G, lt = tid - slot * G;
+        const bool in_slot = slot < cd.nslots;
+        float *A = lds + (size_t)(in_slot ? slot : 0) * 8 * S2;
+
+        // ---- control: claim items for slots that need one -------------------
+        if (in_slot && lt == 0 && need_item) {
+            const int k = atomicAdd(&a.counters[cls], 1);
+            ctrl[slot] = (k < cd.count) ? cd.begin + k : -1;
+        }
+        __syncthreads();
+        if (in_slot && need_item) {
+            item = ctrl[slot];
+            need_item = false;
+            if (item >= 0) {
+                const int4 it = a.items[item];
+                x0 = it.x;
+                y0 = it.y;
+                out = it.w;
+                const int drive = out & 1;
+                hegx = drive == 0 ? a.heg : 0.0f;
+                hegy = drive == 1 ? a.heg : 0.0f;
+                hegx_d = drive == 0 ? a.heg_d : 0.0;
+                hegy_d = drive == 1 ? a.heg_d : 0.0;
+                steps = 0;
+                have_prev = false;
+#pragma unroll
+                for (int k = 0; k < kCPT; ++k) {
+                    const int c = lt + k * G;
+                    if (k < C && c < S2) {
+                        const int x = c % S, y = c / S;
+                        xy[k] = x | (y << 8);
+                        const int fx = (x0 + x) % a.fnx, fy = (y0 + y) % a.fny;
+                        const double kap = a.field[(size_t)fy * a.fnx + fx];
+                        // kappa <= 0 or NaN poisons the item: it ends flagged non-finite
+                        Dc[k] = (kap > 0.0) ? (float)(1.0 / (1.0 + a.h / kap)) : __int_as_float(0x7fc00000);
+                        f0[k] = 0.0f;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) A[q * S2 + c] = 0.0f;
+                    }
+                }
+            }
+        }
+        // ---- all slots idle: next side class, or done -----------------------
+        int busy = 0;
+        __syncthreads();
+        for (int s = 0; s < cd.nslots; ++s) busy |= (ctrl[s] >= 0);
+        if (!busy) {
+            __syncthreads();
+            if (cls + 1 >= a.nclasses) break;
+            ++cls;
+            need_item = true;
+            continue;
+        }
+
+        // ---- check_every steps ----------------------------------------------
+        const bool active = in_slot && item >= 0;
+        for (int st = 0; st < a.check_every; ++st) {
+            if (active) {
+                const bool odd = ((steps + st) & 1) != 0;
+#pragma unroll
+                for (int k = 0; k < kCPT; ++k) {
+                    const int c = lt + k * G;
+                    if (k < C && c < S2) {
+                        const int x = xy[k] & 255, y = xy[k] >> 8;
+                        float f[9];
+                        f[0] = f0[k];
+                        if (!odd) {
+                            // own slots, in order; written back reversed
+#pragma unroll
+                            for (int q = 1; q < 9; ++q) f[q] = A[(q - 1) * S2 + c];
+                            collide(f, Dc[k], hegx, hegy, a);
+                            A[(3 - 1) * S2 + c] = f[1];
+                            A[(4 - 1) * S2 + c] = f[2];
+                            A[(1 - 1) * S2 + c] = f[3];
+                            A[(2 - 1) * S2 + c] = f[4];
+                            A[(7 - 1) * S2 + c] = f[5];
+                            A[(8 - 1) * S2 + c] = f[6];
+                            A[(5 - 1) * S2 + c] = f[7];
+                            A[(6 - 1) * S2 + c] = f[8];
+                        } else {
+                            const int xm = x == 0 ? S - 1 : x - 1, xp = x == S - 1 ? 0 : x + 1;
+                            const int rm = (y == 0 ? S - 1 : y - 1) * S, rp = (y == S - 1 ? 0 : y + 1) * S;
+                            const int r0 = y * S;
+                            // f_a(x) = A[opp a][x - e_a]
+                            f[1] = A[(3 - 1) * S2 + r0 + xm];
+                            f[2] = A[(4 - 1) * S2 + rm + x];
+                            f[3] = A[(1 - 1) * S2 + r0 + xp];
+                            f[4] = A[(2 - 1) * S2 + rp + x];
+                            f[5] = A[(7 - 1) * S2 + rm + xm];
+                            f[6] = A[(8 - 1) * S2 + rm + xp];
+                            f[7] = A[(5 - 1) * S2 + rp + xp];
+                            f[8] = A[(6 - 1) * S2 + rp + xm];
+                            collide(f, Dc[k], hegx, hegy, a);
+                            // f*_a goes to A[a][x + e_a]
+                            A[(1 - 1) * S2 + r0 + xp] = f[1];
+                            A[(2 - 1) * S2 + rp + x] = f[2];
+                            A[(3 - 1) * S2 + r0 + xm] = f[3];
+                            A[(4 - 1) * S2 + rm + x] = f[4];
+                            A[(5 - 1) * S2 + rp + xp] = f[5];
+                            A[(6 - 1) * S2 + rp + xm] = f[6];
+                            A[(7 - 1) * S2 + rm + xm] = f[7];
+                            A[(8 - 1) * S2 + rm + xp] = f[8];
+                        }
+                        f0[k] = f[0];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);  // one cell at a time: bounded register use
+                }
+            }
+            __syncthreads();
+        }
+        if (active) steps += a.check_every;
+
+        // ---- convergence check: FP64 mean velocity of each slot --------------
+        double sx = 0.0, sy = 0.0;
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < kCPT; ++k) {
+                const int c = lt + k * G;
+                if (k < C && c < S2) {
+                    // even order: A[a - 1][c] holds f_a(x) before collision
+                    double fd[9];
+                    fd[0] = f0[k];
+#pragma unroll
+                    for (int q = 1; q < 9; ++q) fd[q] = (double)A[(q - 1) * S2 + c];
+                    const double dr = ((fd[0] + fd[1]) + (fd[2] + fd[3])) + ((fd[4] + fd[5]) + (fd[6] + fd[7])) + fd[8];
+                    const double jx = (fd[1] - fd[3]) + ((fd[5] - fd[6]) + (fd[8] - fd[7]));
+                    const double jy = (fd[2] - fd[4]) + ((fd[5] + fd[6]) - (fd[7] + fd[8]));
+                    const double rho = 1.0 + dr;
+                    const double D = (double)Dc[k];
+                    sx += D * (jx + hegx_d * rho) / rho;
+                    sy += D * (jy + hegy_d * rho) / rho;
+                }
+            }
+        }
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = sx;
+            red[tid >> 6][1] = sy;
+        }
+        __syncthreads();
+        if (active) {
+            const int w0 = (slot * G) >> 6, nw = G >> 6;
+            double tx = 0.0, ty = 0.0;
+            for (int w = 0; w < nw; ++w) {
+                tx += red[w0 + w][0];
+                ty += red[w0 + w][1];
+            }
+            const double ux = tx / S2, uy = ty / S2;
+            int flag = -2;  // -2: keep going
+            if (!isfinite(ux) || !isfinite(uy)) {
+                flag = 2;
+            } else if (have_prev) {
+                const double dx = ux - prev_x, dy = uy - prev_y;
+                if (sqrt(dx * dx + dy * dy) <= a.tol * sqrt(ux * ux + uy * uy)) flag = 0;
+            }
+            if (flag == -2 && steps >= a.max_steps) flag = 1;
+            prev_x = ux;
+            prev_y = uy;
+            have_prev = true;
+            if (flag != -2) {
+                if (lt == 0) {
+                    const int patch = out >> 1, drive = out & 1;
+                    a.keff[4 * (size_t)patch + drive] = a.nu_over_g * ux;
+                    a.keff[4 * (size_t)patch + 2 + drive] = a.nu_over_g * uy;
+                    if (a.steps_out) a.steps_out[2 * patch + drive] = steps;
+                    if (a.flags_out) a.flags_out[2 * patch + drive] = flag;
+                }
+                need_item = true;
+            }
+        }
+        __syncthreads();  // red[] and ctrl[] are reused
+    }
+}
+
+// Entries of skipped drives: NaN K_eff, flag -1, 0 steps.
+__global__ void k_local_prefill(int n, const int *__restrict__ mask, double *__restrict__ keff,
+                                int *__restrict__ steps, int *__restrict__ flags,
+                                int *__restrict__ counters, int ncounters)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncounters) counters[i] = 0;
+    if (i >= n) return;
+    const double qnan = __longlong_as_double(0x7ff8000000000000LL);
+    for (int d = 0; d < 2; ++d) {
+        if (!(mask[i] & (1 << d))) {
+            keff[4 * (size_t)i + d] = qnan;
+            keff[4 * (size_t)i + 2 + d] = qnan;
+            if (steps) steps[2 * i + d] = 0;
+            if (flags) flags[2 * i + d] = -1;
+        }
+    }
+}
+
+struct LocalLayout {
+    size_t off_items, off_classes, off_counters, off_mask, total;
+};
+
+LocalLayout local_layout(int n_patches)
+{
+    LocalLayout L{};
+    size_t off = 0;
+    L.off_items = off;    off = align_up(off + sizeof(int4) * 2 * (size_t)std::max(n_patches, 1));
+    L.off_classes = off;  off = align_up(off + sizeof(ClassDesc) * kMaxClasses);
+    L.off_counters = off; off = align_up(off + sizeof(int) * kMaxClasses);
+    L.off_mask = off;     off = align_up(off + sizeof(int) * (size_t)std::max(n_patches, 1));
+    L.total = off;
+    return L;
+}
+
+int lds_budget_bytes()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        return v;
+    return 64 * 1024;
+}
+
+int pow2_at_least(int v)
+{
+    int p = 64;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+template <int T>
+lbm_status launch_local(const LocalArgs &a, size_t lds_bytes, int grid, hipStream_t stream)
+{
+    if (lds_bytes > 64 * 1024)
+        LBM_HIP(hipFuncSetAttribute((const void *)k_local<T>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    int occ = 0;
+    LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_local<T>, T, lds_bytes));
+    if (occ < 1) return set_error(LBM_EINVAL, "lbm_local_keff: tile does not fit on a CU");
+    const int blocks = std::min(grid, device_cu_count() * occ);
+    hipLaunchKernelGGL(k_local<T>, dim3(blocks), dim3(T), lds_bytes, stream, a);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" int32_t lbm_local_max_side(void) { return kMaxSide; }
+
+extern "C" size_t lbm_local_workspace_bytes(int32_t n_patches)
+{
+    if (n_patches < 0) return 0;
+    return local_layout(n_patches).total;
+}
+
+extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patches, const int32_t *h_x0,
+                                     const int32_t *h_y0, const int32_t *h_side,
+                                     const int32_t *h_drive_mask, const double *d_kappa_field,
+                                     int32_t fnx, int32_t fny, double *d_keff, int32_t *d_steps,
+                                     int32_t *d_flags, const lbm_local_tile *tiles, int32_t n_tiles,
+                                     int32_t block_threads, void *d_ws, size_t ws_bytes,
+                                     hipStream_t stream)
+{
+    const char *fn = "lbm_local_keff: ";
+    if (!lp) return set_error(LBM_EINVAL, std::string(fn) + "params is NULL");
+    if (!(lp->tau >= 0.5) || !std::isfinite(lp->tau)) return set_error(LBM_EINVAL, std::string(fn) + "tau must be >= 0.5");
+    if (!(lp->eps > 0.0 && lp->eps <= 1.0)) return set_error(LBM_EINVAL, std::string(fn) + "eps must lie in (0, 1]");
+    if (!(lp->nu > 0.0) || !std::isfinite(lp->nu)) return set_error(LBM_EINVAL, std::string(fn) + "nu must be > 0");
+    if (!(lp->g > 0.0) || !std::isfinite(lp->g)) return set_error(LBM_EINVAL, std::string(fn) + "g must be > 0");
+    if (!(lp->tol >= 0.0)) return set_error(LBM_EINVAL, std::string(fn) + "tol must be >= 0");
+    if (lp->check_every < 2 || (lp->check_every & 1))
+        return set_error(LBM_EINVAL, std::string(fn) + "check_every must be even and >= 2");
+    if (lp->max_steps < 1 || lp->max_steps > (int64_t)1 << 30)
+        return set_error(LBM_EINVAL, std::string(fn) + "max_steps must lie in [1, 2^30]");
+    if (n_patches < 0) return set_error(LBM_EINVAL, std::string(fn) + "n_patches < 0");
+    if (n_patches == 0) return LBM_OK;
+    if (!h_x0 || !h_y0 || !h_side || !h_drive_mask || !d_kappa_field || !d_keff)
+        return set_error(LBM_EINVAL, std::string(fn) + "NULL array");
+    if (fnx < 1 || fny < 1) return set_error(LBM_EINVAL, std::string(fn) + "field sides must be >= 1");
+    if (block_threads == 0) block_threads = 1024;
+    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
+        return set_error(LBM_EINVAL, std::string(fn) + "block_threads must be 256, 512 or 1024");
+    if (n_tiles < 0 || (n_tiles > 0 && !tiles)) return set_error(LBM_EINVAL, std::string(fn) + "bad tile table");
+    const LocalLayout L = local_layout(n_patches);
+    if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < L.total)
+        return set_error(LBM_EWORKSPACE, std::string(fn) + "workspace NULL, misaligned or smaller than " +
+                                             std::to_string(L.total));
+
+    // items, grouped by side (largest first), drives of one patch adjacent
+    std::vector<int> order(n_patches);
+    std::iota(order.begin(), order.end(), 0);
+    for (int i = 0; i < n_patches; ++i) {
+        if (h_side[i] < 1 || h_side[i] > kMaxSide)
+            return set_error(LBM_EINVAL, std::string(fn) + "patch side must lie in [1, 64]");
+        if (h_drive_mask[i] < 0 || h_drive_mask[i] > 3)
+            return set_error(LBM_EINVAL, std::string(fn) + "drive mask must be 0..3");
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return h_side[p] > h_side[q]; });
+    std::vector<int4> items;
+    items.reserve(2 * (size_t)n_patches);
+    std::vector<ClassDesc> classes;
+    const int T = block_threads;
+    const int budget = lds_budget_bytes() - 2048;
+    size_t lds_max = 0;
+    for (int i : order) {
+        const int s = h_side[i];
+        if (classes.empty() || classes.back().side != s) {
+            ClassDesc c{};
+            c.side = s;
+            c.begin = (int)items.size();
+            int G = 0;
+            for (int t = 0; t < n_tiles; ++t)
+                if (tiles[t].side == s) G = tiles[t].slot_threads;
+            const int cells = s * s;
+            if (G == 0) {
+                const int gmin = pow2_at_least((cells + kCPT - 1) / kCPT);
+                const int fit = std::max(1, budget / (32 * cells));
+                G = std::max(gmin, pow2_at_least((T + fit - 1) / fit));
+                G = std::min(G, T);
+            }
+            if (G < 64 || (G & 63) || G > T || (T % G))
+                return set_error(LBM_EINVAL, std::string(fn) + "slot_threads must be a multiple of 64 dividing block_threads");
+            c.slot_threads = G;
+            c.cells_per_thread = (cells + G - 1) / G;
+            if (c.cells_per_thread > kCPT)
+                return set_error(LBM_EINVAL, std::string(fn) + "tile leaves more than 8 cells per thread (side " +
+                                                     std::to_string(s) + ")");
+            c.nslots = T / G;
+            while (c.nslots > 1 && (size_t)c.nslots * 32 * cells > (size_t)budget) --c.nslots;
+            if ((size_t)32 * cells > (size_t)budget)
+                return set_error(LBM_EINVAL, std::string(fn) + "patch of side " + std::to_string(s) +
+                                                     " does not fit in LDS");
+            lds_max = std::max(lds_max, (size_t)c.nslots * 32 * cells);
+            classes.push_back(c);
+        }
+        for (int d = 0; d < 2; ++d)
+            if (h_drive_mask[i] & (1 << d)) items.push_back(make_int4(h_x0[i] % fnx, h_y0[i] % fny, s, 2 * i + d));
+        classes.back().count = (int)items.size() - classes.back().begin;
+    }
+    // drop classes without items (all drives masked)
+    classes.erase(std::remove_if(classes.begin(), classes.end(), [](const ClassDesc &c) { return c.count == 0; }),
+                  classes.end());
+    if ((int)classes.size() > kMaxClasses) return set_error(LBM_EINVAL, std::string(fn) + "too many sides");
+    for (const int4 &it : items)
+        if (it.x < 0 || it.y < 0) return set_error(LBM_EINVAL, std::string(fn) + "origins must be >= 0");
+
+    char *ws = static_cast<char *>(d_ws);
+    int4 *d_items = reinterpret_cast<int4 *>(ws + L.off_items);
+    ClassDesc *d_classes = reinterpret_cast<ClassDesc *>(ws + L.off_classes);
+    int *d_counters = reinterpret_cast<int *>(ws + L.off_counters);
+    int *d_mask = reinterpret_cast<int *>(ws + L.off_mask);
+    if (!items.empty())
+        LBM_HIP(hipMemcpyAsync(d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, stream));
+    if (!classes.empty())
+        LBM_HIP(hipMemcpyAsync(d_classes, classes.data(), sizeof(ClassDesc) * classes.size(),
+                               hipMemcpyHostToDevice, stream));
+    LBM_HIP(hipMemcpyAsync(d_mask, h_drive_mask, sizeof(int) * n_patches, hipMemcpyHostToDevice, stream));
+    const int nfill = std::max(n_patches, kMaxClasses);
+    hipLaunchKernelGGL(k_local_prefill, dim3((nfill + 255) / 256), dim3(256), 0, stream, n_patches, d_mask,
+                       d_keff, d_steps, d_flags, d_counters, kMaxClasses);
+    LBM_HIP(hipGetLastError());
+    if (items.empty()) return LBM_OK;
+
+    LocalArgs a{};
+    a.items = d_items;
+    a.classes = d_classes;
+    a.nclasses = (int)classes.size();
+    a.counters = d_counters;
+    a.field = d_kappa_field;
+    a.fnx = fnx;
+    a.fny = fny;
+    a.keff = d_keff;
+    a.steps_out = d_steps;
+    a.flags_out = d_flags;
+    a.om = (float)(1.0 / lp->tau);
+    a.omc = (float)(1.0 - 1.0 / lp->tau);
+    a.twotau = (float)(2.0 * lp->tau);
+    a.omtt = (float)(1.0 - 2.0 * lp->tau);
+    a.heg = (float)(0.5 * lp->eps * lp->g);
+    a.heg_d = 0.5 * lp->eps * lp->g;
+    a.h = 0.5 * lp->eps * lp->nu;
+    a.nu_over_g = lp->nu / lp->g;
+    a.tol = lp->tol;
+    a.check_every = lp->check_every;
+    const int64_t ms = (lp->max_steps + lp->check_every - 1) / lp->check_every * lp->check_every;
+    a.max_steps = (int)std::min<int64_t>(ms, (int64_t)1 << 30);
+    // one workgroup per concurrent slot-set: no more than the items need
+    int need = 0;
+    for (const ClassDesc &c : classes) need = std::max(need, (c.count + c.nslots - 1) / c.nslots);
+    const int grid = std::max(1, need);
+    switch (T) {
+    case 256: return launch_local<256>(a, lds_max, grid, stream);
+    case 512: return launch_local<512>(a, lds_max, grid, stream);
+    default: return launch_local<1024>(a, lds_max, grid, stream);
+    }
+}
