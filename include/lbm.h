@@ -209,6 +209,62 @@ lbm_status lbm_coarse_solve(const lbm_params *fine, int32_t r, const double *d_k
                             int64_t *steps_done, void *d_ws, size_t ws_bytes,
                             hipStream_t stream);
 
+/* Mean of every r x r block of nplanes consecutive FP64 fields [plane][ny][nx]
+ * (device) into d_out [plane][ny/r][nx/r] (device), summed in FP64 in a fixed
+ * order: the fine-grid quantity that a coarse cell represents (Sec. 4.3
+ * compares coarse results with fine results averaged over each subdomain).
+ * r must divide nx and ny. Asynchronous. */
+lbm_status lbm_block_average(const double *d_in, int32_t nx, int32_t ny, int32_t nplanes, int32_t r,
+                             double *d_out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned K_eff surrogate (an addition to the paper's method: it learns the
+ * map that the local problems of Sec. 3 compute with Eq. tensor-kappa).
+ *
+ * Network on a periodic 32 x 32 patch of log K, with m = mean(log K):
+ *   x = log K - m; a1 = relu(conv3x3(x; W1, b1))       1 -> 32 channels
+ *   a2..a4 = relu(conv3x3(a; Wl, bl))                   32 -> 32 channels
+ *   z = [mean over pixels of a4, m]; h = relu(M1 z + c1)   (32 hidden units)
+ *   prediction = M2 h + c2 + m  = (log kxx, log kyy)
+ * Convolutions wrap periodically: out[y][x] = sum over taps (dy, dx) in
+ * {-1,0,1}^2 of in[y + dy][x + dx] W[tap], tap = 3 (dy + 1) + (dx + 1).
+ * Parameters: one FP32 vector, in this order:
+ *   W1[9][32], b1[32], then for l = 2, 3, 4: Wl[9][32 ci][32 co], bl[32],
+ *   M1[32][33], c1[32], M2[2][32], c2[2]          (lbm_cnn_param_count() floats)
+ * conv2..4 run on BF16 MFMA with FP32 accumulation; conv1, the head, the
+ * loss and Adam are FP32. Inputs: d_logk FP32 [batch][32][32] (x fastest).
+ * ------------------------------------------------------------------------- */
+
+int32_t lbm_cnn_param_count(void);
+
+/* Workspace for a batch: training != 0 adds the stored activations and
+ * gradient buffers (about 256 KB per patch). */
+size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training);
+
+/* d_pred : FP32 [batch][2] predicted (log kxx, log kyy).
+ * d_stats: FP32 [batch][4] per-patch mean, standard deviation and lag-1
+ *          autocorrelations along x and y of log K (or NULL); used to flag
+ *          patches outside the training distribution. Asynchronous. */
+lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, float *d_pred,
+                           float *d_stats, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Loss = mean over the batch and both outputs of (prediction - target)^2,
+ * d_target FP32 [batch][2] (log kxx, log kyy). Writes d_grad (FP32, one per
+ * parameter, may be NULL), d_loss (one FP32, may be NULL) and the batch's
+ * predictions d_pred. Gradients are summed in a fixed order (deterministic).
+ * Asynchronous. */
+lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, const float *d_logk,
+                             const float *d_target, float *d_grad, float *d_loss, float *d_pred,
+                             void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the
+ * 1-based step count `step`) on the FP32 parameters, with the first and second
+ * moments d_adam_m, d_adam_v (FP32, parameter-sized, zero before step 1).
+ * d_loss (may be NULL) gets the batch loss before the update. Asynchronous. */
+lbm_status lbm_cnn_train_step(float *d_params, float *d_adam_m, float *d_adam_v, int32_t step, float lr,
+                              int32_t batch, const float *d_logk, const float *d_target, float *d_loss,
+                              void *d_ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */

@@ -290,6 +290,28 @@ __global__ __launch_bounds__(kT) void k_coarse_onchip(CoarseArgs<R> a)
 
 __global__ void k_zero_i32c(int *p) { p[0] = 0; }
 
+// Mean of each r x r block of nplanes fields [plane][ny][nx]: one workgroup
+// per output value, fixed-order FP64 sum.
+__global__ __launch_bounds__(256) void k_block_average(const double *__restrict__ in, int nx, int ny, int r,
+                                                       double *__restrict__ out)
+{
+    __shared__ double red[4];
+    const int ncx = nx / r, ncy = ny / r;
+    const int o = blockIdx.x;  // plane * ncx * ncy + J * ncx + I
+    const int plane = o / (ncx * ncy), rem = o % (ncx * ncy);
+    const int J = rem / ncx, I = rem % ncx;
+    const double *f = in + (size_t)plane * nx * ny;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < r * r; k += 256) {
+        const int y = J * r + k / r, x = I * r + k % r;
+        s += f[(size_t)y * nx + x];
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[o] = ((red[0] + red[1]) + (red[2] + red[3])) / ((double)r * r);
+}
+
 struct CoarseLayout {
     bool onchip;
     size_t lds;
@@ -464,4 +486,16 @@ extern "C" lbm_status lbm_coarse_solve(const lbm_params *fine, int32_t r, const 
     }
     lbm_destroy(h);
     return s;
+}
+
+extern "C" lbm_status lbm_block_average(const double *d_in, int32_t nx, int32_t ny, int32_t nplanes, int32_t r,
+                                        double *d_out, hipStream_t stream)
+{
+    if (!d_in || !d_out || nx < 1 || ny < 1 || nplanes < 1 || r < 1 || nx % r || ny % r)
+        return set_error(LBM_EINVAL, "lbm_block_average: NULL pointer, or r does not divide nx and ny");
+    const int64_t nout = (int64_t)nplanes * (nx / r) * (ny / r);
+    if (nout >= (int64_t)1 << 31) return set_error(LBM_EINVAL, "lbm_block_average: too many blocks");
+    hipLaunchKernelGGL(k_block_average, dim3((unsigned)nout), dim3(256), 0, stream, d_in, nx, ny, r, d_out);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
 }

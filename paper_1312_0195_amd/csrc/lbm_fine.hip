@@ -37,6 +37,7 @@ namespace lbm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr size_t kPlanePadBytes = 16384;
 
 template <typename R>
 struct StepArgs {
@@ -109,11 +110,25 @@ __device__ __forceinline__ void moments(const R f[9], R &dr, R &jx, R &jy)
     jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Renumber them so that each XCD gets one contiguous run of row
+// segments: the cache lines that neighbouring segments share (x-shifted
+// populations) and the rows above and below then stay in one L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb)
+{
+    constexpr int kXcd = 8;
+    const int q = nb / kXcd, rem = nb % kXcd;
+    const int k = bid % kXcd, slot = bid / kXcd;
+    return k * q + (k < rem ? k : rem) + slot;
+}
+
 template <typename R, bool WALLS, int PK, bool FF>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
 {
-    const int x = blockIdx.x * kBlock + threadIdx.x;
-    const int y = blockIdx.y;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int nbx = (a.nx + kBlock - 1) / kBlock;
+    const int y = bid / nbx;
+    const int x = (bid - y * nbx) * kBlock + threadIdx.x;
     if (x >= a.nx) return;
     R fr[9];
     pull<R, WALLS>(a.fin, a.stride, a.nx, a.ny, x, y, fr);
@@ -378,7 +393,7 @@ bool params_ok(const lbm_params *p, std::string &why)
 {
     if (!p) { why = "params is NULL"; return false; }
     if (p->nx < 1 || p->ny < 1) { why = "nx and ny must be >= 1"; return false; }
-    if ((int64_t)p->nx * p->ny * 9 >= (int64_t)1 << 31) { why = "grid too large (9 nx ny must be < 2^31)"; return false; }
+    if (9 * ((int64_t)p->nx * p->ny + 8192) >= (int64_t)1 << 31) { why = "grid too large (9 nx ny must be below 2^31 - 73728)"; return false; }
     if (!(p->tau >= 0.5) || !std::isfinite(p->tau)) { why = "tau must be finite and >= 0.5"; return false; }
     if (!(p->eps > 0.0 && p->eps <= 1.0)) { why = "eps must lie in (0, 1]"; return false; }
     if (!(p->nu > 0.0) || !std::isfinite(p->nu)) { why = "nu must be finite and > 0"; return false; }
@@ -395,7 +410,10 @@ Layout layout_of(const lbm_params *p)
     Layout L{};
     const size_t n = (size_t)p->nx * p->ny;
     L.elem = (p->pop_dtype == LBM_F64) ? 8 : 4;
-    L.stride = align_up(n, 64);
+    // Planes are 16 KB apart beyond their size, so that the ten streams of a
+    // step (nine planes and the coefficient) do not start on the same HBM
+    // channels when the plane size is a large power of two.
+    L.stride = align_up(n, 64) + kPlanePadBytes / L.elem;
     L.cstride = n;
     size_t off = 0;
     L.off_a = off;  off = align_up(off + 9 * L.stride * L.elem);
@@ -464,7 +482,7 @@ StepArgs<R> step_args(const lbm_handle *h)
 template <typename R, bool W, int PK, bool FF>
 void launch_step_t(const lbm_handle *h)
 {
-    const dim3 grid(h->L.nbx, h->L.nby);
+    const dim3 grid(h->L.nbx * h->L.nby);
     hipLaunchKernelGGL((k_step<R, W, PK, FF>), grid, dim3(kBlock), 0, h->stream, step_args<R>(h));
 }
 

@@ -1,0 +1,698 @@
+// lbm_surrogate.hip -- learned K_eff surrogate: BF16 MFMA forward and
+// training kernels for gfx950.
+//
+// The network (not part of the paper) maps a periodic 32 x 32 log-permeability
+// patch to log K_eff (xx and yy), the quantity the local problems of Sec. 3
+// compute with Eq. tensor-kappa:
+//   m = mean(log K), x = log K - m                    (FP32)
+//   a1 = relu(conv3x3(x))      1 -> 32 channels      (FP32 VALU: 9-deep)
+//   a2..a4 = relu(conv3x3(.))  32 -> 32 channels     (BF16 MFMA, FP32 accumulate)
+//   p = mean over pixels of a4, z = [p, m]           (FP32)
+//   h = relu(M1 z + c1), y = M2 h + c2, prediction = y + m
+// Convolutions wrap periodically (the local problems are periodic), so the
+// network is invariant to circular shifts of a patch.
+//
+// Parameters are one FP32 vector (layout below). Each launch converts the
+// conv2-4 weights to BF16 in the two layouts the MFMA operands need.
+//
+// Forward: one workgroup (8 waves) per patch at a time, persistent over the
+// batch. Activations stay in LDS ([pixel][channel] BF16, 64 KB per layer,
+// two buffers); a 16x16x32 MFMA takes 16 pixels x 32 input channels of one
+// tap, so a 3x3 layer is 9 MFMAs per 16-pixel x 16-channel output tile. The
+// last conv layer is pooled straight from the accumulators.
+//
+// Training: the forward also stores a1..a4 (BF16) and the pooled features;
+// the head backward runs per patch in FP32; the conv backward walks layers
+// 4 -> 1 per patch with two LDS buffers (layer input and gradient), computing
+//   dW[tap][ci][co] += sum_p X[p + tap][ci] dZ[p][co]        (MFMA, K = pixels)
+//   dX[p][ci] = sum_tap,co dZ[p - tap][co] W[tap][ci][co]   (MFMA, K = channels)
+// Weight gradients accumulate in FP32 registers per workgroup over its
+// patches and are summed over workgroups in a fixed order, so results do not
+// depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+constexpr int kSide = 32;
+constexpr int kPix = kSide * kSide;  // 1024
+constexpr int kC = 32;               // channels
+constexpr int kH = 32;               // hidden units of the head
+constexpr int kT = 512;              // threads per workgroup
+constexpr int kWaves = kT / 64;
+
+// parameter layout (FP32 offsets)
+constexpr int oW1 = 0, oB1 = oW1 + 9 * kC;                  // W1[tap][co]
+constexpr int oW2 = oB1 + kC, oB2 = oW2 + 9 * kC * kC;       // W[tap][ci][co]
+constexpr int oW3 = oB2 + kC, oB3 = oW3 + 9 * kC * kC;
+constexpr int oW4 = oB3 + kC, oB4 = oW4 + 9 * kC * kC;
+constexpr int oM1 = oB4 + kC, oC1 = oM1 + kH * (kC + 1);      // M1[h][33]
+constexpr int oM2 = oC1 + kH, oC2 = oM2 + 2 * kH;             // M2[2][h]
+constexpr int kNParams = oC2 + 2;
+constexpr int kNConv = oM1;               // parameters of the conv layers
+constexpr int kNHead = kNParams - oM1;    // parameters of the head
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wrap32(int v) { return v & (kSide - 1); }
+__device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
+__device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
+
+__device__ __forceinline__ float block_sum_fixed(float v, float *red)
+{
+    // fixed-order sum over the workgroup: wave butterflies, then wave partials
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    float t = 0.0f;
+    for (int w = 0; w < kWaves; ++w) t += red[w];
+    return t;
+}
+
+// BF16 copies of conv2..4 weights:
+//   wf[l][tap][co][ci]  (forward B operand: 8 consecutive ci per lane)
+//   wb[l][tap][ci][co]  (backward-data B operand: 8 consecutive co per lane)
+__global__ void k_pack(const float *__restrict__ prm, __bf16 *__restrict__ wf, __bf16 *__restrict__ wb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * 9 * kC * kC) return;
+    const int l = i / (9 * kC * kC), r = i % (9 * kC * kC);
+    const int tap = r / (kC * kC), ci = (r / kC) % kC, co = r % kC;
+    const float w = prm[oW2 + l * (9 * kC * kC + kC) + r];  // W[tap][ci][co]
+    wf[(size_t)l * 9 * kC * kC + (tap * kC + co) * kC + ci] = (__bf16)w;
+    wb[(size_t)l * 9 * kC * kC + (tap * kC + ci) * kC + co] = (__bf16)w;
+}
+
+struct FwdArgs {
+    const float *prm;
+    const __bf16 *wf;       // [3][9][32][32]
+    const float *logk;      // [B][1024]
+    int batch;
+    float *pred;            // [B][2] log kxx, log kyy
+    float *stats;           // [B][4] mean, std, lag-1 correlation x, y (or null)
+    __bf16 *acts;           // [4][B][1024][32] when training, else null
+    float *pool_out;        // [B][33] pooled features and m when training
+};
+
+// One 3x3, 32 -> 32 layer on MFMA. in/out are [pixel][channel] BF16 in LDS.
+// With POOL the ReLU outputs are summed per channel into pool_part[wave][32]
+// instead of being stored.
+template <bool POOL>
+__device__ __forceinline__ void conv_mfma(const __bf16 *__restrict__ in, __bf16 *__restrict__ out,
+                                          const __bf16 *__restrict__ wfl, const float *__restrict__ bias,
+                                          __bf16 *__restrict__ gout, float *pool_part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;  // n: output channel within tile; g: k-group / row group
+    bf16x8 w[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+            w[t][ct] = *reinterpret_cast<const bf16x8 *>(wfl + (t * kC + ct * 16 + n) * kC + g * 8);
+    const float b0 = bias[n], b1 = bias[16 + n];
+    float ps0 = 0.0f, ps1 = 0.0f;
+    for (int tile = wave; tile < kPix / 16; tile += kWaves) {
+        const int y = tile >> 1, x0 = (tile & 1) * 16;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int p = wrap32(y + tap_dy(t)) * kSide + wrap32(x0 + n + tap_dx(t));
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(in + p * kC + g * 8);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[t][0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[t][1], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = y * kSide + x0 + g * 4 + i;  // D row = pixel within the tile
+            const float v0 = fmaxf(acc0[i] + b0, 0.0f), v1 = fmaxf(acc1[i] + b1, 0.0f);
+            if (POOL) {
+                ps0 += v0;
+                ps1 += v1;
+            } else {
+                out[p * kC + n] = (__bf16)v0;
+                out[p * kC + 16 + n] = (__bf16)v1;
+            }
+            if (gout) {
+                gout[p * kC + n] = (__bf16)v0;
+                gout[p * kC + 16 + n] = (__bf16)v1;
+            }
+        }
+    }
+    if (POOL) {
+        // lanes n, n+16, n+32, n+48 hold the same channel: fixed-order sum
+        ps0 += __shfl_xor(ps0, 16, 64);
+        ps0 += __shfl_xor(ps0, 32, 64);
+        ps1 += __shfl_xor(ps1, 16, 64);
+        ps1 += __shfl_xor(ps1, 32, 64);
+        if (g == 0) {
+            pool_part[wave * kC + n] = ps0;
+            pool_part[wave * kC + 16 + n] = ps1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16 *bufA = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *bufB = bufA + kPix * kC;
+    float *xs = reinterpret_cast<float *>(bufB + kPix * kC);  // [1024]
+    float *pool_part = xs + kPix;                             // [8][32]
+    float *red = pool_part + kWaves * kC;                      // [8]
+    float *head = red + kWaves;                                // [33 + 32]
+    const int tid = threadIdx.x;
+    const float *prm = a.prm;
+
+    for (int b = blockIdx.x; b < a.batch; b += gridDim.x) {
+        // ---- input, centring and statistics (FP32) ----
+        const float *lk = a.logk + (size_t)b * kPix;
+        const float v0 = lk[tid], v1 = lk[tid + kT];
+        const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
+        const float x0 = v0 - m, x1 = v1 - m;
+        xs[tid] = x0;
+        xs[tid + kT] = x1;
+        __syncthreads();
+        if (a.stats) {
+            // variance and lag-1 correlations of the centred field (periodic)
+            const int p0 = tid, p1 = tid + kT;
+            const float rx = x0 * xs[(p0 & ~31) | wrap32(p0 + 1)] + x1 * xs[(p1 & ~31) | wrap32(p1 + 1)];
+            const float ry = x0 * xs[(p0 + kSide) & (kPix - 1)] + x1 * xs[(p1 + kSide) & (kPix - 1)];
+            const float var = block_sum_fixed(x0 * x0 + x1 * x1, red) * (1.0f / kPix);
+            const float cx = block_sum_fixed(rx, red) * (1.0f / kPix);
+            const float cy = block_sum_fixed(ry, red) * (1.0f / kPix);
+            if (tid == 0) {
+                float *s = a.stats + 4 * (size_t)b;
+                s[0] = m;
+                s[1] = sqrtf(var);
+                s[2] = var > 0.f ? cx / var : 0.f;
+                s[3] = var > 0.f ? cy / var : 0.f;
+            }
+        }
+        // ---- conv1: 1 -> 32 channels, FP32 on the VALU ----
+        __bf16 *g1 = a.acts ? a.acts + ((size_t)0 * a.batch + b) * kPix * kC : nullptr;
+        for (int p = tid; p < kPix; p += kT) {
+            const int y = p >> 5, x = p & 31;
+            float nb[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) nb[t] = xs[wrap32(y + tap_dy(t)) * kSide + wrap32(x + tap_dx(t))];
+#pragma unroll
+            for (int co = 0; co < kC; co += 8) {
+                bf16x8 v;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    float z = prm[oB1 + co + j];
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) z += nb[t] * prm[oW1 + t * kC + co + j];
+                    v[j] = (__bf16)fmaxf(z, 0.0f);
+                }
+                *reinterpret_cast<bf16x8 *>(bufA + p * kC + co) = v;
+                if (g1) *reinterpret_cast<bf16x8 *>(g1 + p * kC + co) = v;
+            }
+        }
+        __syncthreads();
+        // ---- conv2..conv4 on MFMA ----
+        __bf16 *g2 = a.acts ? a.acts + ((size_t)1 * a.batch + b) * kPix * kC : nullptr;
+        __bf16 *g3 = a.acts ? a.acts + ((size_t)2 * a.batch + b) * kPix * kC : nullptr;
+        __bf16 *g4 = a.acts ? a.acts + ((size_t)3 * a.batch + b) * kPix * kC : nullptr;
+        conv_mfma<false>(bufA, bufB, a.wf, prm + oB2, g2, pool_part);
+        __syncthreads();
+        conv_mfma<false>(bufB, bufA, a.wf + 9 * kC * kC, prm + oB3, g3, pool_part);
+        __syncthreads();
+        conv_mfma<true>(bufA, nullptr, a.wf + 2 * 9 * kC * kC, prm + oB4, g4, pool_part);
+        __syncthreads();
+        // ---- pooling and head (FP32) ----
+        if (tid < kC) {
+            float s = 0.0f;
+            for (int w = 0; w < kWaves; ++w) s += pool_part[w * kC + tid];
+            head[tid] = s * (1.0f / kPix);
+        }
+        if (tid == 0) head[kC] = m;
+        __syncthreads();
+        if (tid < 64) {
+            // lanes 0..31: hidden units
+            float h = 0.0f;
+            if (tid < kH) {
+                float z = prm[oC1 + tid];
+                for (int k = 0; k <= kC; ++k) z += prm[oM1 + tid * (kC + 1) + k] * head[k];
+                h = fmaxf(z, 0.0f);
+            }
+            float y0 = tid < kH ? prm[oM2 + tid] * h : 0.0f;
+            float y1 = tid < kH ? prm[oM2 + kH + tid] * h : 0.0f;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                y0 += __shfl_xor(y0, off, 64);
+                y1 += __shfl_xor(y1, off, 64);
+            }
+            if (tid == 0) {
+                a.pred[2 * (size_t)b] = y0 + prm[oC2] + m;
+                a.pred[2 * (size_t)b + 1] = y1 + prm[oC2 + 1] + m;
+            }
+            if (a.pool_out && tid <= kC) a.pool_out[(size_t)b * (kC + 1) + tid] = head[tid];
+        }
+        __syncthreads();
+    }
+}
+
+// Head backward per patch (one wave per patch), FP32. Loss L = mean over the
+// batch and both outputs of (prediction - target)^2. Writes the patch's head
+// gradient, dL/dpool and its loss term.
+__global__ __launch_bounds__(64) void k_head_backward(const float *__restrict__ prm,
+                                                      const float *__restrict__ pool, const float *__restrict__ target,
+                                                      int batch, float *__restrict__ ghead,
+                                                      float *__restrict__ dpool, float *__restrict__ loss_terms)
+{
+    const int b = blockIdx.x, j = threadIdx.x;
+    if (b >= batch) return;
+    __shared__ float z[kC + 1], dh[kH], hh[kH];
+    __shared__ float dyv[2];
+    if (j <= kC) z[j] = pool[(size_t)b * (kC + 1) + j];
+    __syncthreads();
+    float hpre = 0.0f, h = 0.0f;
+    if (j < kH) {
+        hpre = prm[oC1 + j];
+        for (int k = 0; k <= kC; ++k) hpre += prm[oM1 + j * (kC + 1) + k] * z[k];
+        h = fmaxf(hpre, 0.0f);
+        hh[j] = h;
+    }
+    float y0 = j < kH ? prm[oM2 + j] * h : 0.0f, y1 = j < kH ? prm[oM2 + kH + j] * h : 0.0f;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        y0 += __shfl_xor(y0, off, 64);
+        y1 += __shfl_xor(y1, off, 64);
+    }
+    const float m = z[kC];
+    const float e0 = y0 + prm[oC2] + m - target[2 * (size_t)b];
+    const float e1 = y1 + prm[oC2 + 1] + m - target[2 * (size_t)b + 1];
+    const float scale = 2.0f / (2.0f * batch);
+    if (j == 0) {
+        dyv[0] = scale * e0;
+        dyv[1] = scale * e1;
+        loss_terms[b] = (e0 * e0 + e1 * e1) / (2.0f * batch);
+    }
+    __syncthreads();
+    float *g = ghead + (size_t)b * kNHead;  // same order as the parameters from oM1
+    if (j < kH) {
+        g[(oM2 - oM1) + j] = dyv[0] * hh[j];
+        g[(oM2 - oM1) + kH + j] = dyv[1] * hh[j];
+        const float d = (hpre > 0.0f) ? (dyv[0] * prm[oM2 + j] + dyv[1] * prm[oM2 + kH + j]) : 0.0f;
+        dh[j] = d;
+        g[(oC1 - oM1) + j] = d;
+        for (int k = 0; k <= kC; ++k) g[j * (kC + 1) + k] = d * z[k];
+    }
+    if (j < 2) g[(oC2 - oM1) + j] = dyv[j];
+    __syncthreads();
+    if (j < kC) {
+        float s = 0.0f;
+        for (int k = 0; k < kH; ++k) s += dh[k] * prm[oM1 + k * (kC + 1) + j];
+        dpool[(size_t)b * kC + j] = s;
+    }
+}
+
+struct BwdArgs {
+    const float *prm;
+    const __bf16 *wb;      // [3][9][ci][co]
+    const float *logk;     // [B][1024]
+    const __bf16 *acts;    // [4][B][1024][32]
+    const float *dpool;    // [B][32]
+    int batch;
+    float *gpart;          // [gridDim.x][kNConv] per-workgroup partial conv gradients
+};
+
+// dW for one 32 -> 32 layer: wave w owns tile-jobs j = w, w + 8, ... of the
+// 36 (tap, co-tile, ci-tile) jobs; each job is a 16 x 16 block of dW[tap]
+// accumulated over the 1024 pixels (K) with D[m = co][n = ci].
+__device__ __forceinline__ void dw_mfma(const __bf16 *__restrict__ X, const __bf16 *__restrict__ dZ, f32x4 acc[5])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    int jj = 0;
+    for (int job = wave; job < 36; job += kWaves, ++jj) {
+        const int tap = job >> 2, cot = (job >> 1) & 1, cit = job & 1;
+        const int dy = tap_dy(tap), dx = tap_dx(tap);
+        f32x4 c = acc[jj];
+        for (int k0 = 0; k0 < kPix; k0 += 32) {
+            bf16x8 av, bv;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int p = k0 + g * 8 + i;  // pixel (K index)
+                av[i] = dZ[p * kC + cot * 16 + n];                       // A[m = co][k = p]
+                const int q = wrap32((p >> 5) + dy) * kSide + wrap32((p & 31) + dx);
+                bv[i] = X[q * kC + cit * 16 + n];                        // B[k = p][n = ci]
+            }
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+        }
+        acc[jj] = c;
+    }
+}
+
+// dX = conv-transpose(dZ, W), times the ReLU mask of X, written over X.
+__device__ __forceinline__ void dx_mfma(__bf16 *__restrict__ X, const __bf16 *__restrict__ dZ,
+                                        const __bf16 *__restrict__ wbl)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    bf16x8 w[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)  // n indexes ci within tile ct; 8 consecutive co per lane
+            w[t][ct] = *reinterpret_cast<const bf16x8 *>(wbl + (t * kC + ct * 16 + n) * kC + g * 8);
+    for (int tile = wave; tile < kPix / 16; tile += kWaves) {
+        const int y = tile >> 1, x0 = (tile & 1) * 16;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            // out[p] uses in[p + tap]: the gradient at p comes from dZ[p - tap]
+            const int p = wrap32(y - tap_dy(t)) * kSide + wrap32(x0 + n - tap_dx(t));
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(dZ + p * kC + g * 8);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w[t][0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w[t][1], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = y * kSide + x0 + g * 4 + i;
+            const float m0 = (float)X[p * kC + n] > 0.0f ? 1.0f : 0.0f;
+            const float m1 = (float)X[p * kC + 16 + n] > 0.0f ? 1.0f : 0.0f;
+            X[p * kC + n] = (__bf16)(acc0[i] * m0);
+            X[p * kC + 16 + n] = (__bf16)(acc1[i] * m1);
+        }
+    }
+}
+
+__device__ __forceinline__ void load_act(__bf16 *__restrict__ dst, const __bf16 *__restrict__ src)
+{
+    const bf16x8 *s = reinterpret_cast<const bf16x8 *>(src);
+    bf16x8 *d = reinterpret_cast<bf16x8 *>(dst);
+    for (int i = threadIdx.x; i < kPix * kC / 8; i += kT) d[i] = s[i];
+}
+
+__global__ __launch_bounds__(kT) void k_backward(BwdArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16 *buf0 = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *buf1 = buf0 + kPix * kC;
+    float *xs = reinterpret_cast<float *>(buf1 + kPix * kC);  // [1024]
+    float *red = xs + kPix;                                   // [8]
+    float *dz1 = red + kWaves;                                // [32] scratch for bias grads
+    const int tid = threadIdx.x;
+    f32x4 acc[3][5];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc[l][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // conv1 weight/bias and conv2..4 bias gradients: thread tid owns entries
+    float gw1[1] = {0.0f};  // W1[tap][co] entry tid (tid < 288)
+    float gb[4] = {0.f, 0.f, 0.f, 0.f};  // bias of layer l for channel tid (tid < 32)
+
+    for (int b = blockIdx.x; b < a.batch; b += gridDim.x) {
+        const size_t stride = (size_t)a.batch * kPix * kC;
+        const __bf16 *act = a.acts + (size_t)b * kPix * kC;
+        // dZ4 = dpool / 1024 where a4 > 0 (a4 from the forward)
+        load_act(buf0, act + 3 * stride);
+        __syncthreads();
+        for (int i = tid; i < kPix * kC; i += kT) {
+            const float d = a.dpool[(size_t)b * kC + (i & 31)] * (1.0f / kPix);
+            buf0[i] = (__bf16)((float)buf0[i] > 0.0f ? d : 0.0f);
+        }
+        __bf16 *dZ = buf0, *X = buf1;
+        for (int l = 3; l >= 1; --l) {  // layer l + 1 of the network: conv2..4 are l = 1..3
+            load_act(X, act + (size_t)(l - 1) * stride);
+            __syncthreads();
+            // bias gradient of this layer: sum over pixels of dZ
+            if (tid < kC) {
+                float s = 0.0f;
+                for (int p = 0; p < kPix; ++p) s += (float)dZ[p * kC + tid];
+                gb[l] += s;
+            }
+            dw_mfma(X, dZ, acc[l - 1]);
+            __syncthreads();
+            dx_mfma(X, dZ, a.wb + (size_t)(l - 1) * 9 * kC * kC);
+            __syncthreads();
+            __bf16 *t = dZ;
+            dZ = X;
+            X = t;
+        }
+        // layer 1 (1 -> 32), FP32: x from the input
+        const float *lk = a.logk + (size_t)b * kPix;
+        const float v0 = lk[tid], v1 = lk[tid + kT];
+        const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
+        xs[tid] = v0 - m;
+        xs[tid + kT] = v1 - m;
+        __syncthreads();
+        if (tid < kC) {
+            float s = 0.0f;
+            for (int p = 0; p < kPix; ++p) s += (float)dZ[p * kC + tid];
+            gb[0] += s;
+        }
+        if (tid < 9 * kC) {
+            const int tap = tid / kC, co = tid % kC;
+            const int dy = tap_dy(tap), dx = tap_dx(tap);
+            float s = 0.0f;
+            for (int p = 0; p < kPix; ++p) {
+                const int q = wrap32((p >> 5) + dy) * kSide + wrap32((p & 31) + dx);
+                s += xs[q] * (float)dZ[p * kC + co];
+            }
+            gw1[0] += s;
+        }
+        __syncthreads();
+    }
+    (void)dz1;
+    // write this workgroup's partial conv gradients
+    float *gp = a.gpart + (size_t)blockIdx.x * kNConv;
+    if (tid < 9 * kC) gp[oW1 + tid] = gw1[0];
+    if (tid < kC) {
+        gp[oB1 + tid] = gb[0];
+        gp[oB2 + tid] = gb[1];
+        gp[oB3 + tid] = gb[2];
+        gp[oB4 + tid] = gb[3];
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        float *gw = gp + oW2 + l * (9 * kC * kC + kC);  // W[tap][ci][co]
+        int jj = 0;
+        for (int job = wave; job < 36; job += kWaves, ++jj) {
+            const int tap = job >> 2, cot = (job >> 1) & 1, cit = job & 1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = cot * 16 + g * 4 + i;  // D row m = co
+                const int ci = cit * 16 + n;          // D col n = ci
+                gw[(tap * kC + ci) * kC + co] = acc[l][jj][i];
+            }
+        }
+    }
+}
+
+// grad = sum over workgroups of the conv partials (fixed order), and the sum
+// over patches of the head gradients; loss = sum of the loss terms.
+__global__ void k_reduce(const float *__restrict__ gpart, int nparts, const float *__restrict__ ghead, int batch,
+                         const float *__restrict__ loss_terms, float *__restrict__ grad, float *__restrict__ loss)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNConv) {
+        float s = 0.0f;
+        for (int w = 0; w < nparts; ++w) s += gpart[(size_t)w * kNConv + i];
+        grad[i] = s;
+    } else if (i < kNParams) {
+        const int j = i - kNConv;
+        float s = 0.0f;
+        for (int b = 0; b < batch; ++b) s += ghead[(size_t)b * kNHead + j];
+        grad[i] = s;
+    } else if (i == kNParams) {
+        float s = 0.0f;
+        for (int b = 0; b < batch; ++b) s += loss_terms[b];
+        *loss = s;
+    }
+}
+
+__global__ void k_adam(float *__restrict__ prm, float *__restrict__ mom, float *__restrict__ vel,
+                       const float *__restrict__ grad, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParams) return;
+    const float g = grad[i];
+    const float m = b1 * mom[i] + (1.0f - b1) * g;
+    const float v = b2 * vel[i] + (1.0f - b2) * g * g;
+    mom[i] = m;
+    vel[i] = v;
+    prm[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+struct SurLayout {
+    size_t off_wf, off_wb, off_acts, off_pool, off_dpool, off_ghead, off_loss_terms, off_gpart, off_grad,
+        off_loss, off_pred, total;
+    int grid;
+};
+
+SurLayout sur_layout(int batch, bool train)
+{
+    SurLayout L{};
+    L.grid = std::max(1, std::min(batch, 256));
+    const size_t B = std::max(batch, 1);
+    size_t off = 0;
+    L.off_wf = off; off = align_up(off + 3 * 9 * kC * kC * 2);
+    L.off_wb = off; off = align_up(off + 3 * 9 * kC * kC * 2);
+    if (train) {
+        L.off_acts = off;       off = align_up(off + 4 * B * kPix * kC * 2);
+        L.off_pool = off;       off = align_up(off + B * (kC + 1) * 4);
+        L.off_dpool = off;      off = align_up(off + B * kC * 4);
+        L.off_ghead = off;      off = align_up(off + B * kNHead * 4);
+        L.off_loss_terms = off; off = align_up(off + B * 4);
+        L.off_gpart = off;      off = align_up(off + (size_t)L.grid * kNConv * 4);
+        L.off_grad = off;       off = align_up(off + kNParams * 4);
+        L.off_loss = off;       off = align_up(off + 4);
+        L.off_pred = off;       off = align_up(off + B * 2 * 4);
+    }
+    L.total = off;
+    return L;
+}
+
+constexpr size_t kFwdLds = 2 * kPix * kC * 2 + (kPix + kWaves * kC + kWaves + 2 * kC + 8) * 4;
+constexpr size_t kBwdLds = 2 * kPix * kC * 2 + (kPix + kWaves + kC) * 4;
+
+lbm_status check_ws(void *d_ws, size_t ws_bytes, size_t need, const char *fn)
+{
+    if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < need)
+        return set_error(LBM_EWORKSPACE, std::string(fn) + ": workspace NULL, misaligned or smaller than " +
+                                             std::to_string(need));
+    return LBM_OK;
+}
+
+lbm_status pack(const float *prm, char *ws, const SurLayout &L, hipStream_t stream)
+{
+    const int n = 3 * 9 * kC * kC;
+    hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, stream, prm,
+                       reinterpret_cast<__bf16 *>(ws + L.off_wf), reinterpret_cast<__bf16 *>(ws + L.off_wb));
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status forward(const float *prm, int batch, const float *logk, float *pred, float *stats, char *ws,
+                   const SurLayout &L, bool train, hipStream_t stream)
+{
+    FwdArgs a{};
+    a.prm = prm;
+    a.wf = reinterpret_cast<const __bf16 *>(ws + L.off_wf);
+    a.logk = logk;
+    a.batch = batch;
+    a.pred = pred;
+    a.stats = stats;
+    a.acts = train ? reinterpret_cast<__bf16 *>(ws + L.off_acts) : nullptr;
+    a.pool_out = train ? reinterpret_cast<float *>(ws + L.off_pool) : nullptr;
+    LBM_HIP(hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds));
+    const int grid = std::max(1, std::min(batch, device_cu_count()));
+    hipLaunchKernelGGL(k_forward, dim3(grid), dim3(kT), kFwdLds, stream, a);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status gradients(const float *prm, int batch, const float *logk, const float *target, float *pred,
+                     char *ws, const SurLayout &L, hipStream_t stream)
+{
+    lbm_status s = pack(prm, ws, L, stream);
+    if (s != LBM_OK) return s;
+    s = forward(prm, batch, logk, pred, nullptr, ws, L, true, stream);
+    if (s != LBM_OK) return s;
+    float *pool = reinterpret_cast<float *>(ws + L.off_pool);
+    float *dpool = reinterpret_cast<float *>(ws + L.off_dpool);
+    float *ghead = reinterpret_cast<float *>(ws + L.off_ghead);
+    float *lterms = reinterpret_cast<float *>(ws + L.off_loss_terms);
+    hipLaunchKernelGGL(k_head_backward, dim3(batch), dim3(64), 0, stream, prm, pool, target, batch, ghead, dpool,
+                       lterms);
+    LBM_HIP(hipGetLastError());
+    BwdArgs b{};
+    b.prm = prm;
+    b.wb = reinterpret_cast<const __bf16 *>(ws + L.off_wb);
+    b.logk = logk;
+    b.acts = reinterpret_cast<const __bf16 *>(ws + L.off_acts);
+    b.dpool = dpool;
+    b.batch = batch;
+    b.gpart = reinterpret_cast<float *>(ws + L.off_gpart);
+    LBM_HIP(hipFuncSetAttribute((const void *)k_backward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBwdLds));
+    hipLaunchKernelGGL(k_backward, dim3(L.grid), dim3(kT), kBwdLds, stream, b);
+    LBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3((kNParams + 1 + 255) / 256), dim3(256), 0, stream,
+                       reinterpret_cast<const float *>(ws + L.off_gpart), L.grid, ghead, batch, lterms,
+                       reinterpret_cast<float *>(ws + L.off_grad), reinterpret_cast<float *>(ws + L.off_loss));
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" int32_t lbm_cnn_param_count(void) { return kNParams; }
+
+extern "C" size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training)
+{
+    if (batch < 1) return 0;
+    return sur_layout(batch, training != 0).total;
+}
+
+extern "C" lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, float *d_pred,
+                                      float *d_stats, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (batch < 1 || !d_params || !d_logk || !d_pred)
+        return set_error(LBM_EINVAL, "lbm_cnn_forward: batch < 1 or NULL argument");
+    const SurLayout L = sur_layout(batch, false);
+    lbm_status s = check_ws(d_ws, ws_bytes, L.total, "lbm_cnn_forward");
+    if (s != LBM_OK) return s;
+    char *ws = static_cast<char *>(d_ws);
+    s = pack(d_params, ws, L, stream);
+    if (s != LBM_OK) return s;
+    return forward(d_params, batch, d_logk, d_pred, d_stats, ws, L, false, stream);
+}
+
+extern "C" lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, const float *d_logk,
+                                        const float *d_target, float *d_grad, float *d_loss, float *d_pred,
+                                        void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (batch < 1 || !d_params || !d_logk || !d_target || !d_pred)
+        return set_error(LBM_EINVAL, "lbm_cnn_gradients: batch < 1 or NULL argument");
+    const SurLayout L = sur_layout(batch, true);
+    lbm_status s = check_ws(d_ws, ws_bytes, L.total, "lbm_cnn_gradients");
+    if (s != LBM_OK) return s;
+    char *ws = static_cast<char *>(d_ws);
+    s = gradients(d_params, batch, d_logk, d_target, d_pred, ws, L, stream);
+    if (s != LBM_OK) return s;
+    if (d_grad)
+        LBM_HIP(hipMemcpyAsync(d_grad, ws + L.off_grad, kNParams * 4, hipMemcpyDeviceToDevice, stream));
+    if (d_loss) LBM_HIP(hipMemcpyAsync(d_loss, ws + L.off_loss, 4, hipMemcpyDeviceToDevice, stream));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_cnn_train_step(float *d_params, float *d_adam_m, float *d_adam_v, int32_t step, float lr,
+                                         int32_t batch, const float *d_logk, const float *d_target, float *d_loss,
+                                         void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (batch < 1 || !d_params || !d_adam_m || !d_adam_v || !d_logk || !d_target || step < 1 || !(lr > 0.0f))
+        return set_error(LBM_EINVAL, "lbm_cnn_train_step: bad argument");
+    const SurLayout L = sur_layout(batch, true);
+    lbm_status s = check_ws(d_ws, ws_bytes, L.total, "lbm_cnn_train_step");
+    if (s != LBM_OK) return s;
+    char *ws = static_cast<char *>(d_ws);
+    float *pred = reinterpret_cast<float *>(ws + L.off_pred);
+    s = gradients(d_params, batch, d_logk, d_target, pred, ws, L, stream);
+    if (s != LBM_OK) return s;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, stream, d_params, d_adam_m, d_adam_v,
+                       reinterpret_cast<const float *>(ws + L.off_grad), lr, b1, b2, 1e-8f, c1, c2);
+    LBM_HIP(hipGetLastError());
+    if (d_loss) LBM_HIP(hipMemcpyAsync(d_loss, ws + L.off_loss, 4, hipMemcpyDeviceToDevice, stream));
+    return LBM_OK;
+}

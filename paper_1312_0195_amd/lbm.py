@@ -27,7 +27,10 @@ EXPORTS = (
     "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_fields", "lbm_get_populations",
     "lbm_set_populations", "lbm_steps_total", "lbm_destroy", "lbm_local_max_side",
     "lbm_local_workspace_bytes", "lbm_local_keff", "lbm_coarse_params",
-    "lbm_coarse_workspace_bytes", "lbm_coarse_solve", "lbm_status_str", "lbm_last_error",
+    "lbm_coarse_workspace_bytes", "lbm_coarse_solve", "lbm_block_average", "lbm_status_str",
+    "lbm_last_error",
+    "lbm_cnn_param_count", "lbm_cnn_workspace_bytes", "lbm_cnn_forward", "lbm_cnn_gradients",
+    "lbm_cnn_train_step",
 )
 
 
@@ -68,6 +71,9 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise LbmError(LBM_EDEVICE, f"{LIB_PATH} is missing: build it with "
                                     "`python -m paper_1312_0195_amd.build`")
+    # torch ships its own HIP runtime; load it first so that liblbm binds to
+    # the same one (two runtimes in one process do not share devices).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     pp = ctypes.POINTER(lbm_params)
     L.lbm_workspace_bytes.argtypes = [pp]
@@ -104,6 +110,21 @@ def lib():
                                    ctypes.c_double, ctypes.c_int32, _vp, _vp,
                                    ctypes.POINTER(ctypes.c_int64), _vp, ctypes.c_size_t, _vp]
     L.lbm_coarse_solve.restype = ctypes.c_int
+    L.lbm_block_average.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, _vp, _vp]
+    L.lbm_block_average.restype = ctypes.c_int
+    L.lbm_cnn_param_count.argtypes = []
+    L.lbm_cnn_param_count.restype = ctypes.c_int32
+    L.lbm_cnn_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.lbm_cnn_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_cnn_forward.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.lbm_cnn_forward.restype = ctypes.c_int
+    L.lbm_cnn_gradients.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp]
+    L.lbm_cnn_gradients.restype = ctypes.c_int
+    L.lbm_cnn_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_int32,
+                                     _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.lbm_cnn_train_step.restype = ctypes.c_int
     L.lbm_status_str.argtypes = [ctypes.c_int]
     L.lbm_status_str.restype = ctypes.c_char_p
     L.lbm_last_error.argtypes = []
@@ -243,6 +264,40 @@ def lbm_coarse_solve(fine: lbm_params, r: int, d_keff, keff_mode: int, d_force, 
     return st, steps.value
 
 
+def lbm_block_average(d_in, nx, ny, nplanes, r, d_out, stream=None) -> None:
+    _raise(lib().lbm_block_average(_ptr(d_in), int(nx), int(ny), int(nplanes), int(r), _ptr(d_out),
+                                   _stream(stream)), "lbm_block_average")
+
+
+def lbm_cnn_param_count() -> int:
+    return int(lib().lbm_cnn_param_count())
+
+
+def lbm_cnn_workspace_bytes(batch: int, training: bool) -> int:
+    return int(lib().lbm_cnn_workspace_bytes(int(batch), int(bool(training))))
+
+
+def lbm_cnn_forward(d_params, batch, d_logk, d_pred, d_stats, d_ws, ws_bytes, stream=None) -> None:
+    _raise(lib().lbm_cnn_forward(_ptr(d_params), int(batch), _ptr(d_logk), _ptr(d_pred),
+                                 _ptr(d_stats), _ptr(d_ws), int(ws_bytes), _stream(stream)),
+           "lbm_cnn_forward")
+
+
+def lbm_cnn_gradients(d_params, batch, d_logk, d_target, d_grad, d_loss, d_pred, d_ws, ws_bytes,
+                      stream=None) -> None:
+    _raise(lib().lbm_cnn_gradients(_ptr(d_params), int(batch), _ptr(d_logk), _ptr(d_target),
+                                   _ptr(d_grad), _ptr(d_loss), _ptr(d_pred), _ptr(d_ws),
+                                   int(ws_bytes), _stream(stream)), "lbm_cnn_gradients")
+
+
+def lbm_cnn_train_step(d_params, d_m, d_v, step, lr, batch, d_logk, d_target, d_loss, d_ws,
+                       ws_bytes, stream=None) -> None:
+    _raise(lib().lbm_cnn_train_step(_ptr(d_params), _ptr(d_m), _ptr(d_v), int(step), float(lr),
+                                    int(batch), _ptr(d_logk), _ptr(d_target), _ptr(d_loss),
+                                    _ptr(d_ws), int(ws_bytes), _stream(stream)),
+           "lbm_cnn_train_step")
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrappers (device memory from torch; no arithmetic of the method)
 # ---------------------------------------------------------------------------
@@ -330,10 +385,14 @@ class LocalResult:
 
 def local_keff(kappa_field, x0, y0, side, tau, eps, nu, g=1e-6, tol=1e-6, check_every=100,
                max_steps=200000, drive_mask=None, tiles=None, block_threads=0, device="cuda",
-               kappa_dev=None) -> LocalResult:
+               kappa_dev=None, use_tuned=True) -> LocalResult:
     """Run lbm_local_keff on a field (host array or device tensor) and return
-    host results."""
+    host results. Without explicit tiles, the autotuned table is used when
+    one exists (see paper_1312_0195_amd.autotune)."""
     import torch
+    if tiles is None and block_threads == 0 and use_tuned:
+        from .autotune import load_table
+        block_threads, tiles = load_table()
     n = len(x0)
     dev = torch.device(device)
     kd = kappa_dev if kappa_dev is not None else torch.as_tensor(

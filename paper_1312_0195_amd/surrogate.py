@@ -1,0 +1,219 @@
+"""Learned K_eff surrogate with the batched local LBM as fallback and judge.
+
+The network (see include/lbm.h, lbm_cnn_*) maps a periodic 32 x 32 patch of
+log K to (log kxx, log kyy) of the effective permeability that the local
+problems of Sec. 3 give through Eq. tensor-kappa. This module:
+
+* builds training data: synthetic log-normal fields (sigma and correlation
+  length drawn per field), cut into 32 x 32 tiles, labelled by
+  lbm_local_keff on the GPU;
+* trains the network on the GPU with the library's own forward, backward and
+  Adam kernels (lbm_cnn_train_step);
+* predicts with lbm_cnn_forward, flags patches whose statistics (standard
+  deviation and lag-1 correlations of log K, computed by the same kernel) fall
+  outside the ranges seen in training, and sends those to lbm_local_keff.
+
+Device memory comes from torch; all arithmetic runs in the HIP library.
+"""
+from __future__ import annotations
+
+import os
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs as I
+from . import lbm as L
+
+SIDE = 32
+PHYS = dict(tau=0.8, eps=0.4, nu=0.1, g=1e-6)
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal initial weights in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    C, H = 32, 32
+    parts = [rng.standard_normal(9 * C) * np.sqrt(2.0 / 9), np.zeros(C)]
+    for _ in range(3):
+        parts += [rng.standard_normal(9 * C * C) * np.sqrt(2.0 / (9 * C)), np.zeros(C)]
+    parts += [rng.standard_normal(H * (C + 1)) * np.sqrt(2.0 / (C + 1)), np.zeros(H),
+              rng.standard_normal(2 * H) * np.sqrt(1.0 / H), np.zeros(2)]
+    v = np.concatenate(parts).astype(np.float32)
+    assert v.size == L.lbm_cnn_param_count()
+    return v
+
+
+# ---------------------------------------------------------------------------
+# Data
+# ---------------------------------------------------------------------------
+
+
+def mosaic(fields):
+    """Place equal square fields side by side in one array (rows of fields)
+    and return it with the 32 x 32 tile origins of every field."""
+    n = fields[0].shape[0]
+    k = len(fields)
+    cols = int(np.ceil(np.sqrt(k)))
+    rows = int(np.ceil(k / cols))
+    big = np.ones((rows * n, cols * n))
+    x0, y0 = [], []
+    for i, f in enumerate(fields):
+        r, c = divmod(i, cols)
+        big[r * n:(r + 1) * n, c * n:(c + 1) * n] = f
+        ty, tx = np.meshgrid(np.arange(0, n, SIDE), np.arange(0, n, SIDE), indexing="ij")
+        x0.append((c * n + tx).ravel())
+        y0.append((r * n + ty).ravel())
+    return big, np.concatenate(x0).astype(np.int32), np.concatenate(y0).astype(np.int32)
+
+
+def label_patches(kappa_big, x0, y0, tol=1e-7, chunk=65536, device="cuda"):
+    """log kxx and log kyy of every 32 x 32 window from the batched LBM."""
+    import torch
+    kd = torch.as_tensor(kappa_big).to(device)
+    out = np.empty((len(x0), 2))
+    flags = np.empty((len(x0), 2), np.int32)
+    for s in range(0, len(x0), chunk):
+        sl = slice(s, s + chunk)
+        side = np.full(len(x0[sl]), SIDE, np.int32)
+        r = L.local_keff(None, x0[sl], y0[sl], side, PHYS["tau"], PHYS["eps"], PHYS["nu"],
+                         PHYS["g"], tol=tol, check_every=100, max_steps=400000, kappa_dev=kd)
+        out[sl, 0] = np.log(r.keff[:, 0])
+        out[sl, 1] = np.log(r.keff[:, 3])
+        flags[sl] = r.flags
+    return out, flags
+
+
+def training_set(n_patches: int, seed: int = 1, field_side: int = 256,
+                 sigma_range=(0.5, 2.5), corr_range=(4.0, 32.0)):
+    """(log K patches [n, 32, 32] FP32, targets [n, 2]) from fields with sigma
+    and correlation length drawn uniformly from the given ranges."""
+    per = (field_side // SIDE) ** 2
+    n_fields = -(-n_patches // per)
+    fields = [f for _, _, f in I.surrogate_fields(n_fields, seed, field_side, sigma_range,
+                                                     corr_range)]
+    big, x0, y0 = mosaic(fields)
+    x0, y0 = x0[:n_patches], y0[:n_patches]
+    y, flags = label_patches(big, x0, y0)
+    ok = (flags == 0).all(axis=1)
+    logk = np.stack([np.log(I.cut_patch(big, a, b, SIDE)) for a, b in zip(x0, y0)])
+    return logk[ok].astype(np.float32), y[ok]
+
+
+# ---------------------------------------------------------------------------
+# The model
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Surrogate:
+    params: np.ndarray
+    stat_lo: np.ndarray = field(default_factory=lambda: np.full(3, -np.inf))
+    stat_hi: np.ndarray = field(default_factory=lambda: np.full(3, np.inf))
+    history: list = field(default_factory=list)
+
+    @classmethod
+    def new(cls, seed: int = 0) -> "Surrogate":
+        return cls(init_params(seed))
+
+    # -- training ----------------------------------------------------------
+    def fit(self, logk, target, epochs=20, batch=256, lr=2e-3, lr_final=1e-4, seed=0,
+            device="cuda", verbose=False):
+        import torch
+        dev = torch.device(device)
+        n = len(logk)
+        X = torch.as_tensor(np.ascontiguousarray(logk, np.float32)).to(dev)
+        Y = torch.as_tensor(np.ascontiguousarray(target, np.float32)).to(dev)
+        prm = torch.as_tensor(self.params).to(dev).contiguous()
+        m = torch.zeros_like(prm)
+        v = torch.zeros_like(prm)
+        nb = L.lbm_cnn_workspace_bytes(batch, True)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        rng = np.random.default_rng(seed)
+        steps_per_epoch = n // batch
+        total = max(1, epochs * steps_per_epoch)
+        step = 0
+        t0 = time.perf_counter()
+        for ep in range(epochs):
+            perm = torch.as_tensor(rng.permutation(n)[:steps_per_epoch * batch]).to(dev)
+            ep_loss = torch.zeros(1, dtype=torch.float32, device=dev)
+            for i in range(steps_per_epoch):
+                idx = perm[i * batch:(i + 1) * batch]
+                xb = X.index_select(0, idx).contiguous()
+                yb = Y.index_select(0, idx).contiguous()
+                step += 1
+                # cosine decay from lr to lr_final
+                cur = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * (step - 1) / total))
+                L.lbm_cnn_train_step(prm, m, v, step, cur, batch, xb, yb, loss, ws, nb)
+                ep_loss += loss
+            torch.cuda.synchronize(dev)
+            mean_loss = float(ep_loss.item()) / max(1, steps_per_epoch)
+            self.history.append(mean_loss)
+            if verbose:
+                print(f"epoch {ep + 1}/{epochs}: loss {mean_loss:.3e} "
+                      f"({time.perf_counter() - t0:.1f} s)", flush=True)
+        self.params = prm.cpu().numpy()
+        # training-distribution ranges of the patch statistics (std, rx, ry)
+        _, stats = self.predict(logk, device=device)
+        s = stats[:, 1:4]
+        lo, hi = np.quantile(s, 0.001, axis=0), np.quantile(s, 0.999, axis=0)
+        pad = 0.05 * (hi - lo)
+        self.stat_lo, self.stat_hi = lo - pad, hi + pad
+        return self
+
+    # -- inference ---------------------------------------------------------
+    def predict(self, logk, device="cuda", batch=65536, stream_ws=None):
+        """(pred [n, 2] log kxx, log kyy; stats [n, 4] mean, std, rx, ry)."""
+        import torch
+        dev = torch.device(device)
+        logk = np.ascontiguousarray(logk, np.float32)
+        n = len(logk)
+        prm = torch.as_tensor(self.params).to(dev)
+        preds, stats = [], []
+        for s in range(0, n, batch):
+            xb = torch.as_tensor(logk[s:s + batch]).to(dev)
+            b = len(xb)
+            pred = torch.empty((b, 2), dtype=torch.float32, device=dev)
+            st = torch.empty((b, 4), dtype=torch.float32, device=dev)
+            nb = L.lbm_cnn_workspace_bytes(b, False)
+            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            L.lbm_cnn_forward(prm, b, xb, pred, st, ws, nb)
+            preds.append(pred.cpu().numpy())
+            stats.append(st.cpu().numpy())
+        return np.concatenate(preds).astype(np.float64), np.concatenate(stats).astype(np.float64)
+
+    def in_range(self, stats) -> np.ndarray:
+        s = np.asarray(stats)[:, 1:4]
+        return ((s >= self.stat_lo) & (s <= self.stat_hi)).all(axis=1)
+
+    def save(self, path):
+        np.savez(path, params=self.params, stat_lo=self.stat_lo, stat_hi=self.stat_hi,
+                 history=np.asarray(self.history))
+
+    @classmethod
+    def load(cls, path) -> "Surrogate":
+        d = np.load(path)
+        return cls(d["params"].astype(np.float32), d["stat_lo"], d["stat_hi"],
+                   list(d["history"]))
+
+
+def keff_with_fallback(model: Surrogate, kappa_big, x0, y0, device="cuda"):
+    """log kxx, log kyy of the 32 x 32 windows at (x0, y0): the network where a
+    patch is in range, the batched LBM (one launch) where it is not.
+    Returns (log_keff [n, 2], used_lbm [n] bool, timings dict)."""
+    import torch
+    t0 = time.perf_counter()
+    logk = np.stack([np.log(I.cut_patch(kappa_big, a, b, SIDE)) for a, b in zip(x0, y0)])
+    t1 = time.perf_counter()
+    pred, stats = model.predict(logk, device=device)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ok = model.in_range(stats)
+    out = pred.copy()
+    if (~ok).any():
+        y, _ = label_patches(kappa_big, x0[~ok], y0[~ok])
+        out[~ok] = y
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    return out, ~ok, dict(cut_s=t1 - t0, network_s=t2 - t1, fallback_s=t3 - t2)

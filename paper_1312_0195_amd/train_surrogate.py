@@ -1,0 +1,163 @@
+"""Train and evaluate the K_eff surrogate on the GPU.
+
+    python -m paper_1312_0195_amd.train_surrogate [--train N] [--epochs E] [--out DIR]
+
+1. Training data: N 32 x 32 tiles of 256 x 256 log-normal fields with sigma
+   ~ U[0.5, 2.5] and correlation length ~ U[4, 32] (new seed per field),
+   labelled by the batched local LBM (lbm_local_keff, both drives).
+2. Training: Adam on the library's BF16-MFMA forward/backward kernels.
+3. Test set: 65536 patches, about 90% from the training distribution (fresh
+   seeds) and 10% outside it (sigma 3.5 at correlation length 8; sigma 1 at
+   correlation length 1.5; 8-row channels of K x 1e3 on a sigma-1 field).
+   Every test patch is also labelled by the LBM, the judge of the network's
+   error. Reported: K_eff error of in-range patches (p50, p95, max), the same
+   for the geometric-mean estimate exp(mean log K), how many patches the
+   range detector sends to the LBM, and patches/s of network + fallback vs
+   the batched LBM alone.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import lbm as L
+from . import surrogate as S
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_MODEL = os.path.join(HERE, "tuning", "surrogate_gfx950.npz")
+
+
+def _fields_to_patches(fields):
+    big, x0, y0 = S.mosaic(fields)
+    return big, x0, y0
+
+
+def test_set(n_total=65536, frac_oor=0.1, seed=12345):
+    """(kappa mosaic, x0, y0, is_oor) with about frac_oor of the patches from
+    out-of-range fields."""
+    per = 64  # 32 x 32 tiles of a 256 x 256 field
+    n_oor_fields = int(round(n_total * frac_oor / per))
+    n_in_fields = n_total // per - n_oor_fields
+    fields = [f for _, _, f in I.surrogate_fields(n_in_fields, seed)]
+    rng = np.random.default_rng(seed + 1)
+    oor = []
+    for i in range(n_oor_fields):
+        kind = i % 3
+        s = int(rng.integers(1 << 30))
+        if kind == 0:
+            oor.append(I.lognormal_kappa(256, 256, 3.5, 8.0, s))
+        elif kind == 1:
+            oor.append(I.lognormal_kappa(256, 256, 1.0, 1.5, s))
+        else:
+            oor.append(I.channelize(I.lognormal_kappa(256, 256, 1.0, 8.0, s), 0.25, 8, 1e3, s))
+    big, x0, y0 = S.mosaic(fields + oor)
+    is_oor = np.zeros(len(x0), bool)
+    is_oor[n_in_fields * per:] = True
+    return big, x0, y0, is_oor
+
+
+def evaluate(model: S.Surrogate, big, x0, y0, is_oor):
+    import torch
+    # LBM labels for every test patch (the judge), timed: the LBM-only path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y_lbm, flags = S.label_patches(big, x0, y0)
+    torch.cuda.synchronize()
+    t_lbm = time.perf_counter() - t0
+    logk = np.stack([np.log(I.cut_patch(big, a, b, S.SIDE)) for a, b in zip(x0, y0)])
+    # network alone (device-resident inputs, kernel time only)
+    X = torch.as_tensor(logk.astype(np.float32)).cuda()
+    prm = torch.as_tensor(model.params).cuda()
+    n = len(x0)
+    pred = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    st = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(n, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_forward(prm, n, X, pred, st, ws, nb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    L.lbm_cnn_forward(prm, n, X, pred, st, ws, nb)
+    e1.record()
+    torch.cuda.synchronize()
+    t_net = e0.elapsed_time(e1) * 1e-3
+    p = pred.cpu().numpy().astype(np.float64)
+    stats = st.cpu().numpy().astype(np.float64)
+    ok = model.in_range(stats)
+    # network + fallback for the flagged patches
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if (~ok).any():
+        yf, _ = S.label_patches(big, x0[~ok], y0[~ok])
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    combined = p.copy()
+    if (~ok).any():
+        combined[~ok] = yf
+    good = (flags == 0).all(axis=1)
+    inr = ok & ~is_oor & good
+    err = np.abs(np.expm1(p[inr] - y_lbm[inr]))  # relative K_eff error
+    geo = np.abs(np.expm1(stats[inr, 0][:, None] - y_lbm[inr]))
+    err_all = np.abs(np.expm1(combined[good] - y_lbm[good]))
+
+    def q(a):
+        return dict(p50=float(np.quantile(a, 0.5)), p95=float(np.quantile(a, 0.95)),
+                    p99=float(np.quantile(a, 0.99)), max=float(a.max()))
+
+    return dict(
+        n_patches=int(n), n_true_oor=int(is_oor.sum()),
+        flagged=int((~ok).sum()), flagged_true_oor=int((~ok & is_oor).sum()),
+        flagged_in_range=int((~ok & ~is_oor).sum()),
+        lbm_label_failures=int((~good).sum()),
+        keff_error_network_in_range=q(err),
+        keff_error_geometric_mean_in_range=q(geo),
+        keff_error_combined_all=q(err_all),
+        seconds_lbm_only=t_lbm, seconds_network=t_net, seconds_fallback=t_fb,
+        patches_per_s_lbm_only=n / t_lbm,
+        patches_per_s_network=n / t_net,
+        patches_per_s_network_plus_fallback=n / (t_net + t_fb),
+    )
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=200_000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--test", type=int, default=65536)
+    ap.add_argument("--model", default=DEFAULT_MODEL)
+    ap.add_argument("--results", default=None)
+    args = ap.parse_args()
+    import torch
+    L.lib()
+    t0 = time.perf_counter()
+    X, Y = S.training_set(args.train, seed=1)
+    t_data = time.perf_counter() - t0
+    print(f"training set: {len(X)} patches labelled in {t_data:.1f} s", flush=True)
+    model = S.Surrogate.new(seed=0)
+    t0 = time.perf_counter()
+    model.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, verbose=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"trained in {t_train:.1f} s", flush=True)
+    os.makedirs(os.path.dirname(args.model), exist_ok=True)
+    model.save(args.model)
+    big, x0, y0, is_oor = test_set(args.test)
+    res = evaluate(model, big, x0, y0, is_oor)
+    res.update(train_patches=int(len(X)), epochs=args.epochs, batch=args.batch,
+               train_seconds=t_train, label_seconds=t_data, final_loss=model.history[-1],
+               loss_history=model.history)
+    print(json.dumps({k: v for k, v in res.items() if k != "loss_history"}), flush=True)
+    if args.results:
+        with open(args.results, "w") as fh:
+            json.dump(res, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+"""GPU parity of the surrogate network kernels (BF16 MFMA, FP32 accumulate)
+against the FP64 numpy oracle, through the C ABI.
+
+Tolerances follow from BF16: activations and conv2-4 weights carry 8
+significant bits (relative rounding 2^-9), so predictions agree to a few
+1e-3 in log K and gradients to cosine >= 0.999 and relative L2 <= 3e-2 per
+parameter tensor.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn_oracle as C
+from paper_1312_0195_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NAMES = ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4", "M1", "c1", "M2", "c2"]
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1312_0195_amd import lbm
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lbm.lib()
+    return lbm
+
+
+def _flat(p):
+    return np.concatenate([p[k].reshape(-1) for k in NAMES]).astype(np.float32)
+
+
+def _unflat(v, like):
+    out, o = {}, 0
+    for k in NAMES:
+        n = like[k].size
+        out[k] = v[o:o + n].reshape(like[k].shape).astype(np.float64)
+        o += n
+    return out
+
+
+def _params(seed):
+    p = C.init_params(C=32, hidden=32, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in ("b1", "b2", "b3", "b4", "c1"):
+        p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    p["c2"] = np.array([0.1, -0.2])
+    return p
+
+
+def _patches(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        f = I.lognormal_kappa(32, 32, float(rng.uniform(0.5, 2.5)), float(rng.uniform(4, 16)),
+                              int(rng.integers(1 << 30)))
+        out.append(np.log(f) + rng.uniform(-2, 2))
+    return np.stack(out)
+
+
+def test_param_count_matches_layout(L):
+    p = _params(0)
+    assert L.lbm_cnn_param_count() == _flat(p).size == 29218
+
+
+@pytest.mark.parametrize("batch", [1, 7, 300])
+def test_forward_matches_oracle(L, batch):
+    p = _params(1)
+    x = _patches(batch, 2)
+    y_o, cache = C.forward(p, x)
+    pred_o = y_o + cache["m"][:, None]
+    prm = torch.tensor(_flat(p), device="cuda")
+    xd = torch.tensor(x.astype(np.float32), device="cuda")
+    pred = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
+    stats = torch.empty((batch, 4), dtype=torch.float32, device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(batch, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_forward(prm, batch, xd, pred, stats, ws, nb)
+    torch.cuda.synchronize()
+    pred = pred.cpu().numpy().astype(np.float64)
+    err = np.abs(pred - pred_o)
+    assert err.max() < 2e-2 * (1 + np.abs(pred_o).max()), err.max()
+    assert np.sqrt((err ** 2).sum() / (pred_o ** 2).sum()) < 5e-3
+    st = stats.cpu().numpy()
+    xc = x - x.mean(axis=(1, 2), keepdims=True)
+    sd = xc.std(axis=(1, 2))
+    assert np.allclose(st[:, 0], x.mean(axis=(1, 2)), rtol=1e-5, atol=1e-5)
+    assert np.allclose(st[:, 1], sd, rtol=1e-4)
+    rx = (xc * np.roll(xc, -1, axis=2)).mean(axis=(1, 2)) / sd ** 2
+    ry = (xc * np.roll(xc, -1, axis=1)).mean(axis=(1, 2)) / sd ** 2
+    assert np.allclose(st[:, 2], rx, atol=1e-4) and np.allclose(st[:, 3], ry, atol=1e-4)
+
+
+def test_forward_shift_invariance_on_gpu(L):
+    p = _params(3)
+    x = _patches(4, 5)
+    xs = np.roll(x, (7, -11), axis=(1, 2))
+    prm = torch.tensor(_flat(p), device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(8, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    both = torch.tensor(np.concatenate([x, xs]).astype(np.float32), device="cuda")
+    pred = torch.empty((8, 2), dtype=torch.float32, device="cuda")
+    L.lbm_cnn_forward(prm, 8, both, pred, None, ws, nb)
+    pr = pred.cpu().numpy()
+    # Invariant in exact arithmetic. On the GPU the patch mean (and the pooled
+    # sums) are added in a different pixel order after a shift, which can move
+    # a BF16 rounding of an activation by one unit: differences stay ~1e-5.
+    assert np.allclose(pr[:4], pr[4:], rtol=0, atol=1e-4)
+
+
+@pytest.mark.parametrize("batch", [3, 64])
+def test_gradients_match_oracle(L, batch):
+    p = _params(4)
+    x = _patches(batch, 6)
+    rng = np.random.default_rng(7)
+    t = x.mean(axis=(1, 2))[:, None] + rng.normal(0.3, 0.5, (batch, 2))
+    y_o, cache = C.forward(p, x)
+    g_o = C.backward(p, cache, y_o, t - cache["m"][:, None])
+    loss_o = C.loss(y_o, t - cache["m"][:, None])
+    prm = torch.tensor(_flat(p), device="cuda")
+    xd = torch.tensor(x.astype(np.float32), device="cuda")
+    td = torch.tensor(t.astype(np.float32), device="cuda")
+    grad = torch.empty_like(prm)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    pred = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(batch, True)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_gradients(prm, batch, xd, td, grad, loss, pred, ws, nb)
+    torch.cuda.synchronize()
+    assert abs(float(loss.item()) - loss_o) < 2e-2 * loss_o
+    g = _unflat(grad.cpu().numpy(), p)
+    for k in NAMES:
+        a, b = g[k].ravel(), g_o[k].ravel()
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300)
+        rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-300)
+        assert cos > 0.999 and rel < 3e-2, (k, cos, rel)
+    # deterministic: the same call gives the same bits
+    grad2 = torch.empty_like(prm)
+    L.lbm_cnn_gradients(prm, batch, xd, td, grad2, loss, pred, ws, nb)
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_step_matches_oracle(L):
+    p = _params(8)
+    x = _patches(16, 9)
+    t = x.mean(axis=(1, 2))[:, None] + 0.5
+    prm = torch.tensor(_flat(p), device="cuda")
+    m = torch.zeros_like(prm)
+    v = torch.zeros_like(prm)
+    xd = torch.tensor(x.astype(np.float32), device="cuda")
+    td = torch.tensor(t.astype(np.float32), device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(16, True)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    grad = torch.empty_like(prm)
+    pred = torch.empty((16, 2), dtype=torch.float32, device="cuda")
+    L.lbm_cnn_gradients(prm, 16, xd, td, grad, None, pred, ws, nb)
+    g = grad.cpu().numpy().astype(np.float64)
+    before = prm.cpu().numpy().astype(np.float64)
+    L.lbm_cnn_train_step(prm, m, v, 1, 1e-3, 16, xd, td, None, ws, nb)
+    torch.cuda.synchronize()
+    ref = {"w": before.copy()}
+    C.adam_step(ref, {"w": g}, {}, lr=1e-3)
+    assert np.allclose(prm.cpu().numpy(), ref["w"], rtol=0, atol=2e-6)
