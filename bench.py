@@ -7,12 +7,14 @@ D2Q9 BGK Brinkman LBM with the Shan-Chen velocity-shift force on a 2048 x 2048
 grid, log-normal permeability K = exp(Z) (Z a seeded periodic Gaussian random
 field, sigma 1.5, correlation length 32 cells), porosity 0.4, tau 0.8,
 nu = nu_eff = 0.1, g = 1e-6 along x, bounce-back walls in y, FP32 deviation
-populations. One step = one fused collide-and-stream pass; the volume-averaged
-velocity (FP64 reduction) is taken every 100 steps inside the timed region.
+populations. Steps run two per launch (temporal blocking through LDS); the
+volume-averaged velocity (FP64 reduction) is taken every 100 steps inside the
+timed region.
 
 Printed: one JSON line with MLUPS (value), the HBM roofline of the step kernel
 measured live with HIP events, the batched local K_eff throughput (patches/s)
-on the 4096 32 x 32 tiles of the same field plus 4096 mixed-size patches, and
+on the 4096 32 x 32 tiles of the same field plus 4096 mixed-size patches, the
+learned K_eff path (network + LBM fallback vs LBM alone, with its error), and
 the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -32,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D2Q9 Brinkman, % HBM roofline); K_eff patches/s surrogate vs LBM @2%"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LU = 76  # 9 x 4 B read + 9 x 4 B written + 4 B drag coefficient
+BYTES_PER_LU = 76  # per cell and launch: 9 x 4 B read + 9 x 4 B written + 4 B drag coefficient
 STEP_KERNEL_SRC = os.path.join(ROOT, "paper_1312_0195_amd", "csrc", "lbm_fine.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fine_step_2048_hbm_counters.md")
 
@@ -73,14 +75,15 @@ def bench_fine(L, torch, kappa, steps, warmup, check_every=100):
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     assert st == L.LBM_OK and done == steps and np.isfinite(mu).all()
-    # step kernel alone: back-to-back launches, no reductions, same stream
-    k = min(steps, 2000)
+    # step kernel alone: back-to-back launches of the two-step kernel, no
+    # reductions, same stream (k even: k / 2 launches)
+    k = max(2, min(steps, 2000) // 2 * 2)
     e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e2.record(stream)
     s.step(k, 0.0, 0)
     e3.record(stream)
     torch.cuda.synchronize()
-    step_ms = e2.elapsed_time(e3) / k
+    step_ms = e2.elapsed_time(e3) / (k // 2)  # per launch (two time steps)
     s.close()
     return dict(wall_s=wall, event_ms=ev_ms, step_kernel_ms=step_ms, mean_u=mu.tolist())
 
@@ -107,6 +110,29 @@ def bench_local(L, torch, kappa_dev, reps=3):
     return out
 
 
+def bench_surrogate(n_test=65536):
+    """The learned K_eff path on a test set of 32 x 32 patches (about 90% from
+    the training distribution, 10% outside it): network, network + batched
+    LBM fallback for flagged patches, and batched LBM alone; K_eff error of
+    the network against the LBM."""
+    from paper_1312_0195_amd import surrogate as S
+    from paper_1312_0195_amd import train_surrogate as T
+    if not os.path.exists(T.DEFAULT_MODEL):
+        return None
+    model = S.Surrogate.load(T.DEFAULT_MODEL)
+    big, x0, y0, is_oor = T.test_set(n_test)
+    r = T.evaluate(model, big, x0, y0, is_oor)
+    e = r["keff_error_network_in_range"]
+    return dict(patches=r["n_patches"], flagged_to_lbm=r["flagged"],
+                patches_per_s_network=r["patches_per_s_network"],
+                patches_per_s_network_plus_fallback=r["patches_per_s_network_plus_fallback"],
+                patches_per_s_lbm_only=r["patches_per_s_lbm_only"],
+                speedup_vs_lbm=r["patches_per_s_network_plus_fallback"] / r["patches_per_s_lbm_only"],
+                keff_rel_error_in_range_p50=e["p50"], keff_rel_error_in_range_p95=e["p95"],
+                keff_rel_error_all_with_fallback=r["keff_error_combined_all"],
+                keff_rel_error_geometric_mean_p50=r["keff_error_geometric_mean_in_range"]["p50"])
+
+
 def cpu_baseline(kappa, steps):
     from oracle import oracle as O
     n = kappa.shape[0]
@@ -126,7 +152,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=600)
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-local", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -159,7 +186,9 @@ def main():
     fine = bench_fine(L, torch, kappa, args.steps, args.warmup)
     ms_per_step = fine["event_ms"] / args.steps
     mlups = cells * args.steps / (fine["event_ms"] * 1e-3) / 1e6
-    step_ms = fine["step_kernel_ms"]
+    step_ms = fine["step_kernel_ms"]  # one launch = two time steps
+    # algorithmic HBM bytes of one launch: the state and the drag coefficient
+    # read once and the state written once, 76 B per cell for two steps
     achieved = BYTES_PER_LU * cells / (step_ms * 1e-3) / 1e9
     traffic = _traffic_per_launch()
     result = {
@@ -181,14 +210,18 @@ def main():
                    "nx": n, "ny": n, "check_every": 100},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step<float, walls, scalar>",
+                     "traffic": traffic,
+                     "kernel": "k_step2<float, walls, scalar> (two time steps per launch)",
                      "avg_launch_us": round(step_ms * 1e3, 3),
-                     "bytes_per_launch": BYTES_PER_LU * cells},
+                     "bytes_per_launch": BYTES_PER_LU * cells,
+                     "lattice_updates_per_launch": 2 * cells},
         "wall_s": round(fine["wall_s"], 3),
     }
     if not args.no_local:
         kd = torch.as_tensor(kappa).cuda()
         result["local_keff"] = bench_local(L, torch, kd)
+    if not args.no_surrogate and not args.no_local:
+        result["keff_surrogate"] = bench_surrogate()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(kappa, args.cpu_steps)
     print(json.dumps(result), flush=True)

@@ -29,6 +29,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "lbm_internal.h"
@@ -122,23 +123,11 @@ __device__ __forceinline__ int xcd_block(int bid, int nb)
     return k * q + (k < rem ? k : rem) + slot;
 }
 
-template <typename R, bool WALLS, int PK, bool FF>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
+// Post-collision values of cell c in place (FP64 arithmetic): the deviation
+// form of Eqs. explicit-u-in-Guo, final-ueq-of-S-C, feq, f-evolution-of-S-C.
+template <typename R, int PK, bool FF>
+__device__ __forceinline__ void collide_cell(const StepArgs<R> &a, double f[9], int c)
 {
-    const int bid = xcd_block(blockIdx.x, gridDim.x);
-    const int nbx = (a.nx + kBlock - 1) / kBlock;
-    const int y = bid / nbx;
-    const int x = (bid - y * nbx) * kBlock + threadIdx.x;
-    if (x >= a.nx) return;
-    R fr[9];
-    pull<R, WALLS>(a.fin, a.stride, a.nx, a.ny, x, y, fr);
-    const int c = y * a.nx + x;
-    // The arithmetic runs in FP64 whatever the storage type: with FP32 storage
-    // the rounding of the collision itself (not of the stored values) is what
-    // limits accuracy, and FP64 VALU work is hidden under the HBM traffic.
-    double f[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = (double)fr[i];
     double dr, jx, jy;
     moments(f, dr, jx, jy);
     const double rho = a.rho0_d + dr;
@@ -170,17 +159,108 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
     const double cx = (1.0 / 12.0) * om * mx;
     const double cy = (1.0 / 12.0) * om * my;
     const double pp = cx + cy, qq = cx - cy;
+    f[0] = omc * f[0] + s0;
+    f[1] = omc * f[1] + (b + bx);
+    f[2] = omc * f[2] + (b + by);
+    f[3] = omc * f[3] + (b - bx);
+    f[4] = omc * f[4] + (b - by);
+    f[5] = omc * f[5] + (cc + pp);
+    f[6] = omc * f[6] + (cc - qq);
+    f[7] = omc * f[7] + (cc - pp);
+    f[8] = omc * f[8] + (cc + qq);
+}
+
+// One time step per launch: pull, collide, store (one HBM pass).
+template <typename R, bool WALLS, int PK, bool FF>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
+{
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int nbx = (a.nx + kBlock - 1) / kBlock;
+    const int y = bid / nbx;
+    const int x = (bid - y * nbx) * kBlock + threadIdx.x;
+    if (x >= a.nx) return;
+    R fr[9];
+    pull<R, WALLS>(a.fin, a.stride, a.nx, a.ny, x, y, fr);
+    const int c = y * a.nx + x;
+    // The arithmetic runs in FP64 whatever the storage type: with FP32 storage
+    // the rounding of the collision itself (not of the stored values) is what
+    // limits accuracy, and FP64 VALU work is hidden under the HBM traffic.
+    double f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = (double)fr[i];
+    collide_cell<R, PK, FF>(a, f, c);
     R *o = a.fout;
     const size_t S = (size_t)a.stride;
-    o[c] = (R)(omc * f[0] + s0);
-    o[S + c] = (R)(omc * f[1] + (b + bx));
-    o[2 * S + c] = (R)(omc * f[2] + (b + by));
-    o[3 * S + c] = (R)(omc * f[3] + (b - bx));
-    o[4 * S + c] = (R)(omc * f[4] + (b - by));
-    o[5 * S + c] = (R)(omc * f[5] + (cc + pp));
-    o[6 * S + c] = (R)(omc * f[6] + (cc - qq));
-    o[7 * S + c] = (R)(omc * f[7] + (cc - pp));
-    o[8 * S + c] = (R)(omc * f[8] + (cc + qq));
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o[q * S + c] = (R)f[q];
+}
+
+// Tile of the two-step kernel: TX x TY output cells per workgroup.
+template <typename R> struct Tile2;
+template <> struct Tile2<float> { static constexpr int TX = 64, TY = 32, BS = 512; };
+template <> struct Tile2<double> { static constexpr int TX = 32, TY = 16, BS = 256; };
+
+// Two time steps per launch (temporal blocking). Phase 1 takes step t on the
+// workgroup's tile plus a one-cell halo, pulling from HBM and keeping the
+// post-collision values in LDS, rounded to the storage type exactly as a
+// store to HBM would round them; phase 2 takes step t + 1 on the tile,
+// pulling from LDS, and writes to HBM. The result is bit-identical to two
+// one-step launches while HBM sees one read and one write of the state per
+// two steps (plus the halo, which neighbouring tiles mostly find in L2).
+template <typename R, bool WALLS, int PK, bool FF>
+__global__ __launch_bounds__(Tile2<R>::BS) void k_step2(StepArgs<R> a)
+{
+    constexpr int TX = Tile2<R>::TX, TY = Tile2<R>::TY, BS = Tile2<R>::BS;
+    constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    __shared__ R h[9][HN];
+    const int nx = a.nx, ny = a.ny;
+    const int ntx = (nx + TX - 1) / TX;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int y0 = (bid / ntx) * TY, x0 = (bid % ntx) * TX;
+    const int tw = min(TX, nx - x0), th = min(TY, ny - y0);  // ragged tiles at the far edges
+    const size_t S = (size_t)a.stride;
+    for (int i = threadIdx.x; i < HN; i += BS) {
+        const int hx = i % HX, hy = i / HX;
+        if (hx > tw + 1 || hy > th + 1) continue;
+        int x = x0 - 1 + hx;
+        x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+        int y = y0 - 1 + hy;
+        if (WALLS) {
+            if (y < 0 || y >= ny) continue;  // beyond a wall: never pulled
+        } else {
+            y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        }
+        R fr[9];
+        pull<R, WALLS>(a.fin, a.stride, nx, ny, x, y, fr);
+        double f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = (double)fr[q];
+        collide_cell<R, PK, FF>(a, f, y * nx + x);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) h[q][i] = (R)f[q];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TX * TY; i += BS) {
+        const int lx = i % TX, ly = i / TX;
+        if (lx >= tw || ly >= th) continue;
+        const int x = x0 + lx, y = y0 + ly;
+        const int c = (ly + 1) * HX + (lx + 1);
+        double f[9];
+        f[0] = (double)h[0][c];
+        f[1] = (double)h[1][c - 1];
+        f[3] = (double)h[3][c + 1];
+        const bool lo = WALLS && y == 0, hi = WALLS && y == ny - 1;
+        f[2] = (double)(lo ? h[4][c] : h[2][c - HX]);
+        f[5] = (double)(lo ? h[7][c] : h[5][c - HX - 1]);
+        f[6] = (double)(lo ? h[8][c] : h[6][c - HX + 1]);
+        f[4] = (double)(hi ? h[2][c] : h[4][c + HX]);
+        f[7] = (double)(hi ? h[5][c] : h[7][c + HX + 1]);
+        f[8] = (double)(hi ? h[6][c] : h[8][c + HX - 1]);
+        const int g = y * nx + x;
+        collide_cell<R, PK, FF>(a, f, g);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) a.fout[q * S + g] = (R)f[q];
+    }
 }
 
 // Flow velocity (Eq. u-of-S-C) and density of the current state in FP64, and
@@ -520,6 +600,15 @@ struct StepFn {
     static void run(const lbm_handle *h) { launch_step_t<R, W, PK, FF>(h); }
 };
 template <typename R, bool W, int PK, bool FF>
+struct Step2Fn {
+    static void run(const lbm_handle *h)
+    {
+        constexpr int TX = Tile2<R>::TX, TY = Tile2<R>::TY, BS = Tile2<R>::BS;
+        const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
+        hipLaunchKernelGGL((k_step2<R, W, PK, FF>), dim3(ntx * nty), dim3(BS), 0, h->stream, step_args<R>(h));
+    }
+};
+template <typename R, bool W, int PK, bool FF>
 struct FieldsFn {
     static void run(const lbm_handle *h, double *u, double *rho, double *part)
     {
@@ -644,10 +733,16 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t max_steps, double tol, int
     bool last_checked = false;
     double u[2] = {0.0, 0.0};
     while (done < max_steps) {
-        dispatch<StepFn>(h);
+        // two steps per launch unless a check or the end falls in between
+        const int64_t to_check = check_every > 0 ? check_every - done % check_every : max_steps - done;
+        const int64_t n = std::min<int64_t>(to_check, max_steps - done) >= 2 ? 2 : 1;
+        if (n == 2)
+            dispatch<Step2Fn>(h);
+        else
+            dispatch<StepFn>(h);
         h->cur ^= 1;
-        ++done;
-        ++h->steps_total;
+        done += n;
+        h->steps_total += n;
         last_checked = false;
         if (check_every > 0 && done % check_every == 0) {
             LBM_HIP(hipGetLastError());
