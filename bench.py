@@ -88,6 +88,29 @@ def bench_fine(L, torch, kappa, steps, warmup, check_every=100):
     return dict(wall_s=wall, event_ms=ev_ms, step_kernel_ms=step_ms, mean_u=mu.tolist())
 
 
+def bench_forms(L, torch, kappa, steps=2000):
+    """Time per step of the two forms of the step on the same workload (Sec.
+    2.1 Guo form vs Sec. 2.2 Shan-Chen form; the paper reports 23 vs 21 min
+    on its CPU code): back-to-back two-step launches, no reductions."""
+    n = kappa.shape[0]
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, scheme in (("shan_chen", L.LBM_SCHEME_SHAN_CHEN), ("guo", L.LBM_SCHEME_GUO)):
+        p = L.make_params(n, n, 0.8, 0.4, 0.1, 1.0, 1e-6, 0.0, 1, L.LBM_F32_SHIFTED,
+                          L.LBM_PERM_SCALAR, scheme)
+        s = L.FineSolver(p, kappa)
+        s.step(200, 0.0, 0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.step(steps, 0.0, 0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name + "_us_per_step"] = round(e0.elapsed_time(e1) * 1e3 / steps, 3)
+        s.close()
+    out["guo_over_shan_chen"] = round(out["guo_us_per_step"] / out["shan_chen_us_per_step"], 4)
+    return out
+
+
 def bench_local(L, torch, kappa_dev, reps=3):
     from paper_1312_0195_amd import inputs as I
     n = kappa_dev.shape[0]
@@ -128,7 +151,10 @@ def bench_surrogate(n_test=65536):
                 patches_per_s_network_plus_fallback=r["patches_per_s_network_plus_fallback"],
                 patches_per_s_lbm_only=r["patches_per_s_lbm_only"],
                 speedup_vs_lbm=r["patches_per_s_network_plus_fallback"] / r["patches_per_s_lbm_only"],
+                n_sym=r["n_sym"],
                 keff_rel_error_in_range_p50=e["p50"], keff_rel_error_in_range_p95=e["p95"],
+                by_n_sym={k: dict(p50=v["p50"], p95=v["p95"], patches_per_s_network=v["patches_per_s"])
+                          for k, v in r["keff_error_in_range_by_n_sym"].items()},
                 keff_rel_error_all_with_fallback=r["keff_error_combined_all"],
                 keff_rel_error_geometric_mean_p50=r["keff_error_geometric_mean_in_range"]["p50"])
 
@@ -217,6 +243,7 @@ def main():
                      "lattice_updates_per_launch": 2 * cells},
         "wall_s": round(fine["wall_s"], 3),
     }
+    result["step_forms"] = bench_forms(L, torch, kappa)
     if not args.no_local:
         kd = torch.as_tensor(kappa).cuda()
         result["local_keff"] = bench_local(L, torch, kd)

@@ -50,6 +50,16 @@ enum {
     LBM_F64 = 1          /* FP64 deviations (reference-precision runs) */
 };
 
+/* Form of the time step. Both give the same populations up to rounding (with
+ * the linear f_eq the two forms are algebraically equal); they differ in cost.
+ * The coarse and local solvers run the Shan-Chen form only. */
+enum {
+    LBM_SCHEME_SHAN_CHEN = 0, /* Sec. 2.2: Eqs. final-ueq-of-S-C, f-evolution-of-S-C */
+    LBM_SCHEME_GUO = 1        /* Sec. 2.1: Eqs. f-evolution-of-Guo, ueq-of-Guo,
+                                 Fi-of-Guo, f_m-depends-on-u, explicit-u-in-Guo;
+                                 scalar permeability only */
+};
+
 /* Kind of permeability given per cell. */
 enum {
     LBM_PERM_SCALAR = 1, /* kappa(x), Eq. f_m-depends-on-u */
@@ -71,6 +81,7 @@ typedef struct {
                           cell below row 0 and above row ny-1 (x is periodic) */
     int32_t pop_dtype; /* LBM_F32_SHIFTED or LBM_F64 */
     int32_t perm_kind; /* LBM_PERM_SCALAR or LBM_PERM_TENSOR */
+    int32_t scheme;    /* LBM_SCHEME_SHAN_CHEN or LBM_SCHEME_GUO (fine solver) */
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -224,15 +235,24 @@ lbm_status lbm_block_average(const double *d_in, int32_t nx, int32_t ny, int32_t
  * Network on a periodic 32 x 32 patch of log K, with m = mean(log K):
  *   x = log K - m; a1 = relu(conv3x3(x; W1, b1))       1 -> 32 channels
  *   a2..a4 = relu(conv3x3(a; Wl, bl))                   32 -> 32 channels
- *   z = [mean over pixels of a4, m]; h = relu(M1 z + c1)   (32 hidden units)
+ *   s = four series/parallel estimates of exp(x), as logs: the mean over rows
+ *       of each row's harmonic mean; the harmonic mean over columns of each
+ *       column's arithmetic mean; the same two with rows and columns exchanged
+ *   z = [mean over pixels of a4, m, s] (37); h = relu(M1 z + c1) (32 hidden)
  *   prediction = M2 h + c2 + m  = (log kxx, log kyy)
  * Convolutions wrap periodically: out[y][x] = sum over taps (dy, dx) in
  * {-1,0,1}^2 of in[y + dy][x + dx] W[tap], tap = 3 (dy + 1) + (dx + 1).
  * Parameters: one FP32 vector, in this order:
  *   W1[9][32], b1[32], then for l = 2, 3, 4: Wl[9][32 ci][32 co], bl[32],
- *   M1[32][33], c1[32], M2[2][32], c2[2]          (lbm_cnn_param_count() floats)
- * conv2..4 run on BF16 MFMA with FP32 accumulation; conv1, the head, the
- * loss and Adam are FP32. Inputs: d_logk FP32 [batch][32][32] (x fastest).
+ *   M1[32][37], c1[32], M2[2][32], c2[2]          (lbm_cnn_param_count() floats)
+ * conv2..4 run on BF16 MFMA with FP32 accumulation; conv1, the features, the
+ * head, the loss and Adam are FP32. Inputs: d_logk FP32 [batch][32][32]
+ * (x fastest).
+ * Symmetries: K_eff transforms with the eight symmetries of the square. A
+ * symmetry code sym = t + 2 fx + 4 fy (0..7) means: output pixel (y, x) of the
+ * transformed patch reads input pixel (v, u), where (u, v) = (x, y), exchanged
+ * if t, then u -> 31 - u if fx and v -> 31 - v if fy; with t the network's
+ * outputs are (log kyy, log kxx) of the original patch.
  * ------------------------------------------------------------------------- */
 
 int32_t lbm_cnn_param_count(void);
@@ -241,29 +261,37 @@ int32_t lbm_cnn_param_count(void);
  * gradient buffers (about 256 KB per patch). */
 size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training);
 
-/* d_pred : FP32 [batch][2] predicted (log kxx, log kyy).
- * d_stats: FP32 [batch][4] per-patch mean, standard deviation and lag-1
- *          autocorrelations along x and y of log K (or NULL); used to flag
- *          patches outside the training distribution. Asynchronous. */
-lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, float *d_pred,
-                           float *d_stats, void *d_ws, size_t ws_bytes, hipStream_t stream);
+/* d_pred : FP32 [batch][2] predicted (log kxx, log kyy) of each patch, the
+ *          mean over symmetry codes 0..n_sym-1 (1 <= n_sym <= 8, else
+ *          LBM_EINVAL) of the network applied to the transformed patch, each
+ *          mapped back to the patch's own axes. n_sym = 1: the plain network.
+ * d_stats: FP32 [batch][8] per-patch mean, standard deviation and lag-1
+ *          autocorrelations along x and y of log K, then the four features s
+ *          (or NULL); used to flag patches outside the training distribution.
+ * Asynchronous. */
+lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
+                           float *d_pred, float *d_stats, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* Loss = mean over the batch and both outputs of (prediction - target)^2,
- * d_target FP32 [batch][2] (log kxx, log kyy). Writes d_grad (FP32, one per
- * parameter, may be NULL), d_loss (one FP32, may be NULL) and the batch's
- * predictions d_pred. Gradients are summed in a fixed order (deterministic).
- * Asynchronous. */
-lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, const float *d_logk,
+ * d_target FP32 [batch][2] (log kxx, log kyy of the untransformed patch).
+ * d_sym: int8 [batch] symmetry code applied to each patch (training-time
+ * augmentation; NULL = none); a transposed patch is compared with the
+ * exchanged target. Writes d_grad (FP32, one per parameter, may be NULL),
+ * d_loss (one FP32, may be NULL) and the batch's predictions d_pred (mapped
+ * back to the untransformed patch's axes, like d_target). Gradients are summed in a fixed order
+ * (deterministic). Asynchronous. */
+lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, const float *d_logk, const int8_t *d_sym,
                              const float *d_target, float *d_grad, float *d_loss, float *d_pred,
                              void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the
  * 1-based step count `step`) on the FP32 parameters, with the first and second
  * moments d_adam_m, d_adam_v (FP32, parameter-sized, zero before step 1).
- * d_loss (may be NULL) gets the batch loss before the update. Asynchronous. */
+ * d_sym as in lbm_cnn_gradients. d_loss (may be NULL) gets the batch loss
+ * before the update. Asynchronous. */
 lbm_status lbm_cnn_train_step(float *d_params, float *d_adam_m, float *d_adam_v, int32_t step, float lr,
-                              int32_t batch, const float *d_logk, const float *d_target, float *d_loss,
-                              void *d_ws, size_t ws_bytes, hipStream_t stream);
+                              int32_t batch, const float *d_logk, const int8_t *d_sym, const float *d_target,
+                              float *d_loss, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Diagnostics

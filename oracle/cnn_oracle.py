@@ -12,9 +12,24 @@ patch -> the diagonal of its effective permeability tensor. Network:
     a3 = relu(conv3x3(a2; W3, b3))
     a4 = relu(conv3x3(a3; W4, b4))
     p  = mean over pixels of a4         (C)
-    z  = [p, mean(log K)]               (C + 1)
+    s  = series/parallel features of k = exp(x) (4, below)
+    z  = [p, mean(log K), s]            (C + 5)
     h  = relu(M1 z + c1)                (hidden)
     y  = M2 h + c2                      (2: log kxx - mean, log kyy - mean)
+
+The four features are the logs of the classical series-parallel estimates of
+an effective permeability of k = exp(x) (rows along x, columns along y):
+    sx_lo = log mean_rows(harmonic mean along the row)
+    sx_up = log harmonic mean over columns(arithmetic mean along the column)
+    sy_lo = log mean_columns(harmonic mean along the column)
+    sy_up = log harmonic mean over rows(arithmetic mean along the row)
+(for Darcy flow they bound kxx and kyy; here they are only inputs).
+
+Symmetry: K_eff is equivariant under the eight symmetries of the square
+(pinned in the LBM oracle tests): with sym = t + 2 fx + 4 fy, output pixel
+(y, x) of the transformed patch reads input pixel (v, u) where (u, v) = (x, y)
+swapped if t, then u -> W-1-u if fx, v -> H-1-v if fy; a transposition
+(t = 1) swaps kxx and kyy.
 
 Convolutions wrap around the patch edges (circular padding), matching the
 periodic local problems, so the network is exactly invariant to circular
@@ -30,6 +45,34 @@ import numpy as np
 TAPS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 
 
+NFEAT = 5  # mean(log K) and the four series/parallel features
+
+
+def transform(logk, sym):
+    """Apply symmetry sym (0..7) to patches [B, H, W] (see the module text)."""
+    t, fx, fy = sym & 1, (sym >> 1) & 1, (sym >> 2) & 1
+    a = np.asarray(logk)
+    # the mirrors act on the source indices (u, v), so they come first
+    if fx:
+        a = a[:, :, ::-1]
+    if fy:
+        a = a[:, ::-1, :]
+    if t:
+        a = np.swapaxes(a, 1, 2)
+    return np.ascontiguousarray(a)
+
+
+def series_parallel(x):
+    """The four features of centred patches x [B, H, W]."""
+    k = np.exp(x)
+    row_h = 1.0 / np.mean(1.0 / k, axis=2)   # harmonic along x, per row
+    col_a = np.mean(k, axis=1)                # arithmetic along y, per column
+    col_h = 1.0 / np.mean(1.0 / k, axis=1)
+    row_a = np.mean(k, axis=2)
+    return np.stack([np.log(row_h.mean(axis=1)), -np.log(np.mean(1.0 / col_a, axis=1)),
+                     np.log(col_h.mean(axis=1)), -np.log(np.mean(1.0 / row_a, axis=1))], axis=1)
+
+
 def init_params(C: int = 32, hidden: int = 32, seed: int = 0) -> dict:
     """He-normal weights, zero biases (FP64)."""
     rng = np.random.default_rng(seed)
@@ -39,7 +82,7 @@ def init_params(C: int = 32, hidden: int = 32, seed: int = 0) -> dict:
         p[f"W{l}"] = rng.standard_normal((9, cin, C)) * np.sqrt(2.0 / (9 * cin))
         p[f"b{l}"] = np.zeros(C)
         cin = C
-    p["M1"] = rng.standard_normal((hidden, C + 1)) * np.sqrt(2.0 / (C + 1))
+    p["M1"] = rng.standard_normal((hidden, C + NFEAT)) * np.sqrt(2.0 / (C + NFEAT))
     p["c1"] = np.zeros(hidden)
     p["M2"] = rng.standard_normal((2, hidden)) * np.sqrt(1.0 / hidden)
     p["c2"] = np.zeros(2)
@@ -73,7 +116,8 @@ def conv3x3_backward(a, W, g):
 
 
 def forward(p: dict, logk: np.ndarray):
-    """logk: [B, H, W] FP64. Returns (y [B, 2], cache)."""
+    """logk: [B, H, W] FP64 (already transformed, if a symmetry is used).
+    Returns (y [B, 2], cache)."""
     logk = np.asarray(logk, dtype=np.float64)
     m = logk.mean(axis=(1, 2))
     x = (logk - m[:, None, None])[..., None]
@@ -86,7 +130,7 @@ def forward(p: dict, logk: np.ndarray):
         a = np.maximum(z, 0.0)
         acts.append(a)
     pool = a.mean(axis=(1, 2))
-    zin = np.concatenate([pool, m[:, None]], axis=1)
+    zin = np.concatenate([pool, m[:, None], series_parallel(x[..., 0])], axis=1)
     hpre = zin @ p["M1"].T + p["c1"]
     h = np.maximum(hpre, 0.0)
     y = h @ p["M2"].T + p["c2"]
@@ -134,9 +178,20 @@ def adam_step(p: dict, g: dict, state: dict, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
 
 
+def predict_symmetric(p: dict, logk: np.ndarray, n_sym: int = 8) -> np.ndarray:
+    """log K_eff prediction averaged over the first n_sym symmetries, each
+    mapped back to the original axes: [B, 2]."""
+    out = np.zeros((len(logk), 2))
+    for sym in range(n_sym):
+        y, c = forward(p, transform(logk, sym))
+        pred = y + c["m"][:, None]
+        out += pred[:, ::-1] if sym & 1 else pred
+    return out / n_sym
+
+
 def flops_forward(H=32, W=32, C=32, hidden=32) -> int:
     """Multiply-adds x 2 of one forward pass."""
     n = H * W
     conv = 2 * n * 9 * (1 * C + 3 * C * C)
-    mlp = 2 * (hidden * (C + 1) + 2 * hidden)
+    mlp = 2 * (hidden * (C + NFEAT) + 2 * hidden)
     return conv + mlp

@@ -417,6 +417,7 @@ extern "C" lbm_status lbm_coarse_solve(const lbm_params *fine, int32_t r, const 
     lbm_params pc{};
     lbm_status s = lbm_coarse_params(fine, r, &pc);
     if (s != LBM_OK) return s;
+    if (fine->scheme != LBM_SCHEME_SHAN_CHEN) return set_error(LBM_EINVAL, fn + "the coarse solver runs the Shan-Chen form (scheme 0)");
     if (!d_keff || !d_u) return set_error(LBM_EINVAL, fn + "NULL keff or u");
     if (keff_mode != LBM_KEFF_SCALAR && keff_mode != LBM_KEFF_TENSOR) return set_error(LBM_EINVAL, fn + "bad keff_mode");
     if (check_every < 2 || (check_every & 1)) return set_error(LBM_EINVAL, fn + "check_every must be even and >= 2");

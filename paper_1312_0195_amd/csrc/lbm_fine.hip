@@ -125,9 +125,54 @@ __device__ __forceinline__ int xcd_block(int bid, int nb)
 
 // Post-collision values of cell c in place (FP64 arithmetic): the deviation
 // form of Eqs. explicit-u-in-Guo, final-ueq-of-S-C, feq, f-evolution-of-S-C.
+// The Guo form (Sec. 2.1) taken literally, for the cost comparison of the two
+// forms: u from Eq. explicit-u-in-Guo (one division), the drag force f_m of
+// Eq. f_m-depends-on-u, f_eq at u (Eq. feq), the forcing term F_a of Eq.
+// Fi-of-Guo and the update of Eq. f-evolution-of-Guo. coef holds eps nu / kappa.
+template <typename R, bool FF>
+__device__ __forceinline__ void collide_cell_guo(const StepArgs<R> &a, double f[9], int c)
+{
+    double dr, jx, jy;
+    moments(f, dr, jx, jy);
+    const double rho = a.rho0_d + dr;
+    double hgx, hgy;  // eps G / 2
+    if (FF) {
+        hgx = (double)a.hforce[c];
+        hgy = (double)a.hforce[a.cstride + c];
+    } else {
+        hgx = a.hegx_d;
+        hgy = a.hegy_d;
+    }
+    const double cnu = (double)a.coef[c];
+    const double den = rho * (1.0 + 0.5 * cnu);
+    const double ux = (jx + hgx * rho) / den, uy = (jy + hgy * rho) / den;
+    // rho f_m = rho (eps G - (eps nu / kappa) u)
+    const double fmx = rho * (2.0 * hgx - cnu * ux), fmy = rho * (2.0 * hgy - cnu * uy);
+    const double om = a.om_d;
+    const double kf = 3.0 * (1.0 - 0.5 * om);  // (1 - 1/(2 tau)) / c_s^2
+    const double ru3x = 3.0 * rho * ux, ru3y = 3.0 * rho * uy;
+    // deviations: f~eq_a = w_a (dr + 3 rho e_a . u), F_a = w_a kf e_a . rho f_m
+    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w5 = 1.0 / 36.0;
+    f[0] = f[0] + om * (w0 * dr - f[0]);
+    f[1] = f[1] + om * (w1 * (dr + ru3x) - f[1]) + w1 * kf * fmx;
+    f[2] = f[2] + om * (w1 * (dr + ru3y) - f[2]) + w1 * kf * fmy;
+    f[3] = f[3] + om * (w1 * (dr - ru3x) - f[3]) - w1 * kf * fmx;
+    f[4] = f[4] + om * (w1 * (dr - ru3y) - f[4]) - w1 * kf * fmy;
+    f[5] = f[5] + om * (w5 * (dr + ru3x + ru3y) - f[5]) + w5 * kf * (fmx + fmy);
+    f[6] = f[6] + om * (w5 * (dr - ru3x + ru3y) - f[6]) + w5 * kf * (fmy - fmx);
+    f[7] = f[7] + om * (w5 * (dr - ru3x - ru3y) - f[7]) - w5 * kf * (fmx + fmy);
+    f[8] = f[8] + om * (w5 * (dr + ru3x - ru3y) - f[8]) + w5 * kf * (fmx - fmy);
+}
+
+// PK: 1 scalar drag coefficient D, 4 tensor M (Shan-Chen form); 0 the Guo
+// form with coef = eps nu / kappa.
 template <typename R, int PK, bool FF>
 __device__ __forceinline__ void collide_cell(const StepArgs<R> &a, double f[9], int c)
 {
+    if (PK == 0) {
+        collide_cell_guo<R, FF>(a, f, c);
+        return;
+    }
     double dr, jx, jy;
     moments(f, dr, jx, jy);
     const double rho = a.rho0_d + dr;
@@ -296,6 +341,10 @@ __global__ __launch_bounds__(kBlock) void k_fields(StepArgs<R> a, double *__rest
             const double D = (double)a.coef[c];
             ux = D * hx / rho;
             uy = D * hy / rho;
+        } else if (PK == 0) {
+            const double den = rho * (1.0 + 0.5 * (double)a.coef[c]);
+            ux = hx / den;
+            uy = hy / den;
         } else {
             const double m00 = a.coef[c], m01 = a.coef[a.cstride + c];
             const double m10 = a.coef[2 * a.cstride + c], m11 = a.coef[3 * a.cstride + c];
@@ -385,6 +434,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ perm
         if (!(k > 0.0)) atomicOr(bad, 1);  // also catches NaN
         // D = 1 / (1 + eps nu / (2 kappa)); kappa = +inf gives 1
         coef[c] = (R)(1.0 / (1.0 + h / k));
+    } else if (PK == 0) {
+        const double k = perm[c];
+        if (!(k > 0.0)) atomicOr(bad, 1);
+        coef[c] = (R)(2.0 * h / k);  // eps nu / kappa (Guo form)
     } else {
         const double kxx = perm[4 * c], kxy = perm[4 * c + 1];
         const double kyx = perm[4 * c + 2], kyy = perm[4 * c + 3];
@@ -482,6 +535,8 @@ bool params_ok(const lbm_params *p, std::string &why)
     if (p->walls_y != 0 && p->walls_y != 1) { why = "walls_y must be 0 or 1"; return false; }
     if (p->pop_dtype != LBM_F32_SHIFTED && p->pop_dtype != LBM_F64) { why = "unknown pop_dtype"; return false; }
     if (p->perm_kind != LBM_PERM_SCALAR && p->perm_kind != LBM_PERM_TENSOR) { why = "perm_kind must be 1 or 4"; return false; }
+    if (p->scheme != LBM_SCHEME_SHAN_CHEN && p->scheme != LBM_SCHEME_GUO) { why = "scheme must be 0 or 1"; return false; }
+    if (p->scheme == LBM_SCHEME_GUO && p->perm_kind != LBM_PERM_SCALAR) { why = "the Guo form takes a scalar permeability"; return false; }
     return true;
 }
 
@@ -578,19 +633,24 @@ void launch_fields_t(const lbm_handle *h, double *u, double *rho, double *part)
 template <template <typename, bool, int, bool> class Fn, typename... Args>
 void dispatch(const lbm_handle *h, Args... args)
 {
-    const bool w = h->p.walls_y != 0, ff = h->has_force, t = h->p.perm_kind == LBM_PERM_TENSOR;
+    const bool w = h->p.walls_y != 0, ff = h->has_force;
+    const int pk = h->p.scheme == LBM_SCHEME_GUO ? 0 : h->p.perm_kind;
 #define LBM_CASE(R, W, PK, FF) \
-    if (w == W && t == (PK == 4) && ff == FF) { Fn<R, W, PK, FF>::run(h, args...); return; }
+    if (w == W && pk == PK && ff == FF) { Fn<R, W, PK, FF>::run(h, args...); return; }
     if (h->p.pop_dtype == LBM_F64) {
         LBM_CASE(double, false, 1, false) LBM_CASE(double, false, 1, true)
         LBM_CASE(double, false, 4, false) LBM_CASE(double, false, 4, true)
         LBM_CASE(double, true, 1, false)  LBM_CASE(double, true, 1, true)
         LBM_CASE(double, true, 4, false)  LBM_CASE(double, true, 4, true)
+        LBM_CASE(double, false, 0, false) LBM_CASE(double, false, 0, true)
+        LBM_CASE(double, true, 0, false)  LBM_CASE(double, true, 0, true)
     } else {
         LBM_CASE(float, false, 1, false) LBM_CASE(float, false, 1, true)
         LBM_CASE(float, false, 4, false) LBM_CASE(float, false, 4, true)
         LBM_CASE(float, true, 1, false)  LBM_CASE(float, true, 1, true)
         LBM_CASE(float, true, 4, false)  LBM_CASE(float, true, 4, true)
+        LBM_CASE(float, false, 0, false) LBM_CASE(float, false, 0, true)
+        LBM_CASE(float, true, 0, false)  LBM_CASE(float, true, 0, true)
     }
 #undef LBM_CASE
 }
@@ -681,7 +741,10 @@ extern "C" lbm_status lbm_init(lbm_handle **out, const lbm_params *p, const doub
             double *coef = reinterpret_cast<double *>(h->ws + L.off_coef);
             double *hf = reinterpret_cast<double *>(h->ws + L.off_force);
             double *pa = reinterpret_cast<double *>(h->ws + L.off_a);
-            if (p->perm_kind == LBM_PERM_SCALAR)
+            if (p->scheme == LBM_SCHEME_GUO)
+                hipLaunchKernelGGL((k_init<double, 0>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
+                                   p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
+            else if (p->perm_kind == LBM_PERM_SCALAR)
                 hipLaunchKernelGGL((k_init<double, 1>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
                                    p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
             else
@@ -691,7 +754,10 @@ extern "C" lbm_status lbm_init(lbm_handle **out, const lbm_params *p, const doub
             float *coef = reinterpret_cast<float *>(h->ws + L.off_coef);
             float *hf = reinterpret_cast<float *>(h->ws + L.off_force);
             float *pa = reinterpret_cast<float *>(h->ws + L.off_a);
-            if (p->perm_kind == LBM_PERM_SCALAR)
+            if (p->scheme == LBM_SCHEME_GUO)
+                hipLaunchKernelGGL((k_init<float, 0>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
+                                   p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
+            else if (p->perm_kind == LBM_PERM_SCALAR)
                 hipLaunchKernelGGL((k_init<float, 1>), dim3(nb), dim3(kBlock), 0, stream, d_perm, d_force, n,
                                    p->eps, p->nu, coef, hf, (int)L.cstride, pa, (int)L.stride, flag);
             else

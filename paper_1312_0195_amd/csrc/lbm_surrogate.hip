@@ -7,8 +7,16 @@
 //   m = mean(log K), x = log K - m                    (FP32)
 //   a1 = relu(conv3x3(x))      1 -> 32 channels      (FP32 VALU: 9-deep)
 //   a2..a4 = relu(conv3x3(.))  32 -> 32 channels     (BF16 MFMA, FP32 accumulate)
-//   p = mean over pixels of a4, z = [p, m]           (FP32)
-//   h = relu(M1 z + c1), y = M2 h + c2, prediction = y + m
+//   p = mean over pixels of a4                       (FP32)
+//   s = log series/parallel estimates of exp(x)      (FP32, 4 values:
+//       mean over rows of the harmonic mean along each row; harmonic mean over
+//       columns of the arithmetic mean along each column; and the same with
+//       rows and columns exchanged)
+//   z = [p, m, s], h = relu(M1 z + c1), y = M2 h + c2, prediction = y + m
+// A symmetry of the square can be applied to a patch as it is read (sym =
+// t + 2 fx + 4 fy: transpose, then mirror x, then mirror y); a transposition
+// exchanges the kxx and kyy outputs. Training draws one per patch (given by
+// the caller); inference can average the prediction over all eight.
 // Convolutions wrap periodically (the local problems are periodic), so the
 // network is invariant to circular shifts of a patch.
 //
@@ -52,7 +60,8 @@ constexpr int oW1 = 0, oB1 = oW1 + 9 * kC;                  // W1[tap][co]
 constexpr int oW2 = oB1 + kC, oB2 = oW2 + 9 * kC * kC;       // W[tap][ci][co]
 constexpr int oW3 = oB2 + kC, oB3 = oW3 + 9 * kC * kC;
 constexpr int oW4 = oB3 + kC, oB4 = oW4 + 9 * kC * kC;
-constexpr int oM1 = oB4 + kC, oC1 = oM1 + kH * (kC + 1);      // M1[h][33]
+constexpr int kZ = kC + 5;                                     // head input size
+constexpr int oM1 = oB4 + kC, oC1 = oM1 + kH * kZ;            // M1[h][37]
 constexpr int oM2 = oC1 + kH, oC2 = oM2 + 2 * kH;             // M2[2][h]
 constexpr int kNParams = oC2 + 2;
 constexpr int kNConv = oM1;               // parameters of the conv layers
@@ -64,6 +73,53 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int wrap32(int v) { return v & (kSide - 1); }
 __device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
 __device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
+
+// Input pixel read for output pixel p under symmetry sym.
+__device__ __forceinline__ int sym_src(int p, int sym)
+{
+    int u = p & 31, v = p >> 5;
+    if (sym & 1) {
+        const int t = u;
+        u = v;
+        v = t;
+    }
+    if (sym & 2) u = 31 - u;
+    if (sym & 4) v = 31 - v;
+    return v * kSide + u;
+}
+
+// The four series/parallel features of k = exp(x) from the centred patch in
+// LDS: threads 0..31 take rows, 32..63 columns; fixed-order sums.
+__device__ __forceinline__ void series_parallel(const float *xs, float *lane_tmp, float *feat)
+{
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const int r = tid & 31;
+        float hs = 0.0f, as = 0.0f;  // sums of 1/k and k along the line
+        for (int i = 0; i < kSide; ++i) {
+            const float x = tid < 32 ? xs[r * kSide + i] : xs[i * kSide + r];
+            hs += __expf(-x);
+            as += __expf(x);
+        }
+        lane_tmp[tid] = kSide / hs;        // harmonic mean of the line
+        lane_tmp[64 + tid] = as / kSide;   // arithmetic mean of the line
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float rh = 0.f, ch = 0.f, ria = 0.f, cia = 0.f;
+        for (int i = 0; i < 32; ++i) {
+            rh += lane_tmp[i];                  // rows: harmonic along x
+            ch += lane_tmp[32 + i];             // columns: harmonic along y
+            cia += 1.0f / lane_tmp[64 + 32 + i];  // columns: arithmetic along y
+            ria += 1.0f / lane_tmp[64 + i];       // rows: arithmetic along x
+        }
+        feat[0] = logf(rh / 32.0f);
+        feat[1] = -logf(cia / 32.0f);
+        feat[2] = logf(ch / 32.0f);
+        feat[3] = -logf(ria / 32.0f);
+    }
+    __syncthreads();
+}
 
 __device__ __forceinline__ float block_sum_fixed(float v, float *red)
 {
@@ -97,11 +153,13 @@ struct FwdArgs {
     const float *prm;
     const __bf16 *wf;       // [3][9][32][32]
     const float *logk;      // [B][1024]
+    const int8_t *sym;      // [B] symmetry per patch (training) or null
+    int n_sym;              // predictions averaged over symmetries 0..n_sym-1
     int batch;
     float *pred;            // [B][2] log kxx, log kyy
-    float *stats;           // [B][4] mean, std, lag-1 correlation x, y (or null)
+    float *stats;           // [B][8] mean, std, lag-1 corr x, y, the 4 features (or null)
     __bf16 *acts;           // [4][B][1024][32] when training, else null
-    float *pool_out;        // [B][33] pooled features and m when training
+    float *pool_out;        // [B][37] head input when training
 };
 
 // One 3x3, 32 -> 32 layer on MFMA. in/out are [pixel][channel] BF16 in LDS.
@@ -170,97 +228,108 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     float *xs = reinterpret_cast<float *>(bufB + kPix * kC);  // [1024]
     float *pool_part = xs + kPix;                             // [8][32]
     float *red = pool_part + kWaves * kC;                      // [8]
-    float *head = red + kWaves;                                // [33 + 32]
+    float *head = red + kWaves;                                // [37]
+    float *tmp = head + kZ + 3;                                // [128]
     const int tid = threadIdx.x;
     const float *prm = a.prm;
 
     for (int b = blockIdx.x; b < a.batch; b += gridDim.x) {
-        // ---- input, centring and statistics (FP32) ----
         const float *lk = a.logk + (size_t)b * kPix;
-        const float v0 = lk[tid], v1 = lk[tid + kT];
-        const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
-        const float x0 = v0 - m, x1 = v1 - m;
-        xs[tid] = x0;
-        xs[tid + kT] = x1;
-        __syncthreads();
-        if (a.stats) {
-            // variance and lag-1 correlations of the centred field (periodic)
-            const int p0 = tid, p1 = tid + kT;
-            const float rx = x0 * xs[(p0 & ~31) | wrap32(p0 + 1)] + x1 * xs[(p1 & ~31) | wrap32(p1 + 1)];
-            const float ry = x0 * xs[(p0 + kSide) & (kPix - 1)] + x1 * xs[(p1 + kSide) & (kPix - 1)];
-            const float var = block_sum_fixed(x0 * x0 + x1 * x1, red) * (1.0f / kPix);
-            const float cx = block_sum_fixed(rx, red) * (1.0f / kPix);
-            const float cy = block_sum_fixed(ry, red) * (1.0f / kPix);
-            if (tid == 0) {
-                float *s = a.stats + 4 * (size_t)b;
-                s[0] = m;
-                s[1] = sqrtf(var);
-                s[2] = var > 0.f ? cx / var : 0.f;
-                s[3] = var > 0.f ? cy / var : 0.f;
-            }
-        }
-        // ---- conv1: 1 -> 32 channels, FP32 on the VALU ----
-        __bf16 *g1 = a.acts ? a.acts + ((size_t)0 * a.batch + b) * kPix * kC : nullptr;
-        for (int p = tid; p < kPix; p += kT) {
-            const int y = p >> 5, x = p & 31;
-            float nb[9];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) nb[t] = xs[wrap32(y + tap_dy(t)) * kSide + wrap32(x + tap_dx(t))];
-#pragma unroll
-            for (int co = 0; co < kC; co += 8) {
-                bf16x8 v;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    float z = prm[oB1 + co + j];
-#pragma unroll
-                    for (int t = 0; t < 9; ++t) z += nb[t] * prm[oW1 + t * kC + co + j];
-                    v[j] = (__bf16)fmaxf(z, 0.0f);
+        float acc0 = 0.0f, acc1 = 0.0f;  // averaged prediction (thread 0)
+        for (int t = 0; t < a.n_sym; ++t) {
+            const int sym = a.sym ? (int)a.sym[b] : t;
+            // ---- input under the symmetry, centring (FP32) ----
+            const float v0 = lk[sym_src(tid, sym)], v1 = lk[sym_src(tid + kT, sym)];
+            const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
+            const float x0 = v0 - m, x1 = v1 - m;
+            xs[tid] = x0;
+            xs[tid + kT] = x1;
+            __syncthreads();
+            if (a.stats && t == 0) {
+                // variance and lag-1 correlations of the centred field (periodic)
+                const int p0 = tid, p1 = tid + kT;
+                const float rx = x0 * xs[(p0 & ~31) | wrap32(p0 + 1)] + x1 * xs[(p1 & ~31) | wrap32(p1 + 1)];
+                const float ry = x0 * xs[(p0 + kSide) & (kPix - 1)] + x1 * xs[(p1 + kSide) & (kPix - 1)];
+                const float var = block_sum_fixed(x0 * x0 + x1 * x1, red) * (1.0f / kPix);
+                const float cx = block_sum_fixed(rx, red) * (1.0f / kPix);
+                const float cy = block_sum_fixed(ry, red) * (1.0f / kPix);
+                if (tid == 0) {
+                    float *st = a.stats + 8 * (size_t)b;
+                    st[0] = m;
+                    st[1] = sqrtf(var);
+                    st[2] = var > 0.f ? cx / var : 0.f;
+                    st[3] = var > 0.f ? cy / var : 0.f;
                 }
-                *reinterpret_cast<bf16x8 *>(bufA + p * kC + co) = v;
-                if (g1) *reinterpret_cast<bf16x8 *>(g1 + p * kC + co) = v;
             }
-        }
-        __syncthreads();
-        // ---- conv2..conv4 on MFMA ----
-        __bf16 *g2 = a.acts ? a.acts + ((size_t)1 * a.batch + b) * kPix * kC : nullptr;
-        __bf16 *g3 = a.acts ? a.acts + ((size_t)2 * a.batch + b) * kPix * kC : nullptr;
-        __bf16 *g4 = a.acts ? a.acts + ((size_t)3 * a.batch + b) * kPix * kC : nullptr;
-        conv_mfma<false>(bufA, bufB, a.wf, prm + oB2, g2, pool_part);
-        __syncthreads();
-        conv_mfma<false>(bufB, bufA, a.wf + 9 * kC * kC, prm + oB3, g3, pool_part);
-        __syncthreads();
-        conv_mfma<true>(bufA, nullptr, a.wf + 2 * 9 * kC * kC, prm + oB4, g4, pool_part);
-        __syncthreads();
-        // ---- pooling and head (FP32) ----
-        if (tid < kC) {
-            float s = 0.0f;
-            for (int w = 0; w < kWaves; ++w) s += pool_part[w * kC + tid];
-            head[tid] = s * (1.0f / kPix);
-        }
-        if (tid == 0) head[kC] = m;
-        __syncthreads();
-        if (tid < 64) {
-            // lanes 0..31: hidden units
-            float h = 0.0f;
-            if (tid < kH) {
-                float z = prm[oC1 + tid];
-                for (int k = 0; k <= kC; ++k) z += prm[oM1 + tid * (kC + 1) + k] * head[k];
-                h = fmaxf(z, 0.0f);
-            }
-            float y0 = tid < kH ? prm[oM2 + tid] * h : 0.0f;
-            float y1 = tid < kH ? prm[oM2 + kH + tid] * h : 0.0f;
+            series_parallel(xs, tmp, head + kC + 1);
+            if (a.stats && t == 0 && tid < 4) a.stats[8 * (size_t)b + 4 + tid] = head[kC + 1 + tid];
+            // ---- conv1: 1 -> 32 channels, FP32 on the VALU ----
+            __bf16 *g1 = a.acts ? a.acts + ((size_t)0 * a.batch + b) * kPix * kC : nullptr;
+            for (int p = tid; p < kPix; p += kT) {
+                const int y = p >> 5, x = p & 31;
+                float nb[9];
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                y0 += __shfl_xor(y0, off, 64);
-                y1 += __shfl_xor(y1, off, 64);
+                for (int q = 0; q < 9; ++q) nb[q] = xs[wrap32(y + tap_dy(q)) * kSide + wrap32(x + tap_dx(q))];
+#pragma unroll
+                for (int co = 0; co < kC; co += 8) {
+                    bf16x8 v;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        float z = prm[oB1 + co + j];
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) z += nb[q] * prm[oW1 + q * kC + co + j];
+                        v[j] = (__bf16)fmaxf(z, 0.0f);
+                    }
+                    *reinterpret_cast<bf16x8 *>(bufA + p * kC + co) = v;
+                    if (g1) *reinterpret_cast<bf16x8 *>(g1 + p * kC + co) = v;
+                }
             }
-            if (tid == 0) {
-                a.pred[2 * (size_t)b] = y0 + prm[oC2] + m;
-                a.pred[2 * (size_t)b + 1] = y1 + prm[oC2 + 1] + m;
+            __syncthreads();
+            // ---- conv2..conv4 on MFMA ----
+            __bf16 *g2 = a.acts ? a.acts + ((size_t)1 * a.batch + b) * kPix * kC : nullptr;
+            __bf16 *g3 = a.acts ? a.acts + ((size_t)2 * a.batch + b) * kPix * kC : nullptr;
+            __bf16 *g4 = a.acts ? a.acts + ((size_t)3 * a.batch + b) * kPix * kC : nullptr;
+            conv_mfma<false>(bufA, bufB, a.wf, prm + oB2, g2, pool_part);
+            __syncthreads();
+            conv_mfma<false>(bufB, bufA, a.wf + 9 * kC * kC, prm + oB3, g3, pool_part);
+            __syncthreads();
+            conv_mfma<true>(bufA, nullptr, a.wf + 2 * 9 * kC * kC, prm + oB4, g4, pool_part);
+            __syncthreads();
+            // ---- pooling and head (FP32) ----
+            if (tid < kC) {
+                float sp = 0.0f;
+                for (int w = 0; w < kWaves; ++w) sp += pool_part[w * kC + tid];
+                head[tid] = sp * (1.0f / kPix);
             }
-            if (a.pool_out && tid <= kC) a.pool_out[(size_t)b * (kC + 1) + tid] = head[tid];
+            if (tid == 0) head[kC] = m;
+            __syncthreads();
+            if (tid < 64) {
+                float hval = 0.0f;
+                if (tid < kH) {
+                    float z = prm[oC1 + tid];
+                    for (int k = 0; k < kZ; ++k) z += prm[oM1 + tid * kZ + k] * head[k];
+                    hval = fmaxf(z, 0.0f);
+                }
+                float y0 = tid < kH ? prm[oM2 + tid] * hval : 0.0f;
+                float y1 = tid < kH ? prm[oM2 + kH + tid] * hval : 0.0f;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    y0 += __shfl_xor(y0, off, 64);
+                    y1 += __shfl_xor(y1, off, 64);
+                }
+                y0 += prm[oC2] + m;
+                y1 += prm[oC2 + 1] + m;
+                // a transposed patch predicts (kyy, kxx) of the original
+                acc0 += (sym & 1) ? y1 : y0;
+                acc1 += (sym & 1) ? y0 : y1;
+                if (a.pool_out && tid < kZ) a.pool_out[(size_t)b * kZ + tid] = head[tid];
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        if (tid == 0) {
+            a.pred[2 * (size_t)b] = acc0 / a.n_sym;
+            a.pred[2 * (size_t)b + 1] = acc1 / a.n_sym;
+        }
     }
 }
 
@@ -269,19 +338,20 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
 // gradient, dL/dpool and its loss term.
 __global__ __launch_bounds__(64) void k_head_backward(const float *__restrict__ prm,
                                                       const float *__restrict__ pool, const float *__restrict__ target,
-                                                      int batch, float *__restrict__ ghead,
-                                                      float *__restrict__ dpool, float *__restrict__ loss_terms)
+                                                      const int8_t *__restrict__ sym, int batch,
+                                                      float *__restrict__ ghead, float *__restrict__ dpool,
+                                                      float *__restrict__ loss_terms)
 {
     const int b = blockIdx.x, j = threadIdx.x;
     if (b >= batch) return;
-    __shared__ float z[kC + 1], dh[kH], hh[kH];
+    __shared__ float z[kZ], dh[kH], hh[kH];
     __shared__ float dyv[2];
-    if (j <= kC) z[j] = pool[(size_t)b * (kC + 1) + j];
+    if (j < kZ) z[j] = pool[(size_t)b * kZ + j];
     __syncthreads();
     float hpre = 0.0f, h = 0.0f;
     if (j < kH) {
         hpre = prm[oC1 + j];
-        for (int k = 0; k <= kC; ++k) hpre += prm[oM1 + j * (kC + 1) + k] * z[k];
+        for (int k = 0; k < kZ; ++k) hpre += prm[oM1 + j * kZ + k] * z[k];
         h = fmaxf(hpre, 0.0f);
         hh[j] = h;
     }
@@ -292,8 +362,10 @@ __global__ __launch_bounds__(64) void k_head_backward(const float *__restrict__ 
         y1 += __shfl_xor(y1, off, 64);
     }
     const float m = z[kC];
-    const float e0 = y0 + prm[oC2] + m - target[2 * (size_t)b];
-    const float e1 = y1 + prm[oC2 + 1] + m - target[2 * (size_t)b + 1];
+    // a transposed patch is trained on the exchanged targets
+    const int tr = (sym && (sym[b] & 1)) ? 1 : 0;
+    const float e0 = y0 + prm[oC2] + m - target[2 * (size_t)b + tr];
+    const float e1 = y1 + prm[oC2 + 1] + m - target[2 * (size_t)b + 1 - tr];
     const float scale = 2.0f / (2.0f * batch);
     if (j == 0) {
         dyv[0] = scale * e0;
@@ -308,13 +380,13 @@ __global__ __launch_bounds__(64) void k_head_backward(const float *__restrict__ 
         const float d = (hpre > 0.0f) ? (dyv[0] * prm[oM2 + j] + dyv[1] * prm[oM2 + kH + j]) : 0.0f;
         dh[j] = d;
         g[(oC1 - oM1) + j] = d;
-        for (int k = 0; k <= kC; ++k) g[j * (kC + 1) + k] = d * z[k];
+        for (int k = 0; k < kZ; ++k) g[j * kZ + k] = d * z[k];
     }
     if (j < 2) g[(oC2 - oM1) + j] = dyv[j];
     __syncthreads();
     if (j < kC) {
         float s = 0.0f;
-        for (int k = 0; k < kH; ++k) s += dh[k] * prm[oM1 + k * (kC + 1) + j];
+        for (int k = 0; k < kH; ++k) s += dh[k] * prm[oM1 + k * kZ + j];
         dpool[(size_t)b * kC + j] = s;
     }
 }
@@ -323,6 +395,7 @@ struct BwdArgs {
     const float *prm;
     const __bf16 *wb;      // [3][9][ci][co]
     const float *logk;     // [B][1024]
+    const int8_t *sym;     // [B] or null
     const __bf16 *acts;    // [4][B][1024][32]
     const float *dpool;    // [B][32]
     int batch;
@@ -445,7 +518,8 @@ __global__ __launch_bounds__(kT) void k_backward(BwdArgs a)
         }
         // layer 1 (1 -> 32), FP32: x from the input
         const float *lk = a.logk + (size_t)b * kPix;
-        const float v0 = lk[tid], v1 = lk[tid + kT];
+        const int sym = a.sym ? (int)a.sym[b] : 0;
+        const float v0 = lk[sym_src(tid, sym)], v1 = lk[sym_src(tid + kT, sym)];
         const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
         xs[tid] = v0 - m;
         xs[tid + kT] = v1 - m;
@@ -546,7 +620,7 @@ SurLayout sur_layout(int batch, bool train)
     L.off_wb = off; off = align_up(off + 3 * 9 * kC * kC * 2);
     if (train) {
         L.off_acts = off;       off = align_up(off + 4 * B * kPix * kC * 2);
-        L.off_pool = off;       off = align_up(off + B * (kC + 1) * 4);
+        L.off_pool = off;       off = align_up(off + B * kZ * 4);
         L.off_dpool = off;      off = align_up(off + B * kC * 4);
         L.off_ghead = off;      off = align_up(off + B * kNHead * 4);
         L.off_loss_terms = off; off = align_up(off + B * 4);
@@ -559,7 +633,7 @@ SurLayout sur_layout(int batch, bool train)
     return L;
 }
 
-constexpr size_t kFwdLds = 2 * kPix * kC * 2 + (kPix + kWaves * kC + kWaves + 2 * kC + 8) * 4;
+constexpr size_t kFwdLds = 2 * kPix * kC * 2 + (kPix + kWaves * kC + kWaves + kZ + 3 + 128) * 4;
 constexpr size_t kBwdLds = 2 * kPix * kC * 2 + (kPix + kWaves + kC) * 4;
 
 lbm_status check_ws(void *d_ws, size_t ws_bytes, size_t need, const char *fn)
@@ -579,13 +653,15 @@ lbm_status pack(const float *prm, char *ws, const SurLayout &L, hipStream_t stre
     return LBM_OK;
 }
 
-lbm_status forward(const float *prm, int batch, const float *logk, float *pred, float *stats, char *ws,
-                   const SurLayout &L, bool train, hipStream_t stream)
+lbm_status forward(const float *prm, int batch, const float *logk, const int8_t *sym, int n_sym, float *pred,
+                   float *stats, char *ws, const SurLayout &L, bool train, hipStream_t stream)
 {
     FwdArgs a{};
     a.prm = prm;
     a.wf = reinterpret_cast<const __bf16 *>(ws + L.off_wf);
     a.logk = logk;
+    a.sym = sym;
+    a.n_sym = sym ? 1 : n_sym;
     a.batch = batch;
     a.pred = pred;
     a.stats = stats;
@@ -598,24 +674,25 @@ lbm_status forward(const float *prm, int batch, const float *logk, float *pred, 
     return LBM_OK;
 }
 
-lbm_status gradients(const float *prm, int batch, const float *logk, const float *target, float *pred,
-                     char *ws, const SurLayout &L, hipStream_t stream)
+lbm_status gradients(const float *prm, int batch, const float *logk, const int8_t *sym, const float *target,
+                     float *pred, char *ws, const SurLayout &L, hipStream_t stream)
 {
     lbm_status s = pack(prm, ws, L, stream);
     if (s != LBM_OK) return s;
-    s = forward(prm, batch, logk, pred, nullptr, ws, L, true, stream);
+    s = forward(prm, batch, logk, sym, 1, pred, nullptr, ws, L, true, stream);
     if (s != LBM_OK) return s;
     float *pool = reinterpret_cast<float *>(ws + L.off_pool);
     float *dpool = reinterpret_cast<float *>(ws + L.off_dpool);
     float *ghead = reinterpret_cast<float *>(ws + L.off_ghead);
     float *lterms = reinterpret_cast<float *>(ws + L.off_loss_terms);
-    hipLaunchKernelGGL(k_head_backward, dim3(batch), dim3(64), 0, stream, prm, pool, target, batch, ghead, dpool,
-                       lterms);
+    hipLaunchKernelGGL(k_head_backward, dim3(batch), dim3(64), 0, stream, prm, pool, target, sym, batch, ghead,
+                       dpool, lterms);
     LBM_HIP(hipGetLastError());
     BwdArgs b{};
     b.prm = prm;
     b.wb = reinterpret_cast<const __bf16 *>(ws + L.off_wb);
     b.logk = logk;
+    b.sym = sym;
     b.acts = reinterpret_cast<const __bf16 *>(ws + L.off_acts);
     b.dpool = dpool;
     b.batch = batch;
@@ -643,23 +720,25 @@ extern "C" size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training)
     return sur_layout(batch, training != 0).total;
 }
 
-extern "C" lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, float *d_pred,
-                                      float *d_stats, void *d_ws, size_t ws_bytes, hipStream_t stream)
+extern "C" lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
+                                      float *d_pred, float *d_stats, void *d_ws, size_t ws_bytes,
+                                      hipStream_t stream)
 {
     if (batch < 1 || !d_params || !d_logk || !d_pred)
         return set_error(LBM_EINVAL, "lbm_cnn_forward: batch < 1 or NULL argument");
+    if (n_sym < 1 || n_sym > 8) return set_error(LBM_EINVAL, "lbm_cnn_forward: n_sym must lie in [1, 8]");
     const SurLayout L = sur_layout(batch, false);
     lbm_status s = check_ws(d_ws, ws_bytes, L.total, "lbm_cnn_forward");
     if (s != LBM_OK) return s;
     char *ws = static_cast<char *>(d_ws);
     s = pack(d_params, ws, L, stream);
     if (s != LBM_OK) return s;
-    return forward(d_params, batch, d_logk, d_pred, d_stats, ws, L, false, stream);
+    return forward(d_params, batch, d_logk, nullptr, n_sym, d_pred, d_stats, ws, L, false, stream);
 }
 
 extern "C" lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, const float *d_logk,
-                                        const float *d_target, float *d_grad, float *d_loss, float *d_pred,
-                                        void *d_ws, size_t ws_bytes, hipStream_t stream)
+                                        const int8_t *d_sym, const float *d_target, float *d_grad, float *d_loss,
+                                        float *d_pred, void *d_ws, size_t ws_bytes, hipStream_t stream)
 {
     if (batch < 1 || !d_params || !d_logk || !d_target || !d_pred)
         return set_error(LBM_EINVAL, "lbm_cnn_gradients: batch < 1 or NULL argument");
@@ -667,7 +746,7 @@ extern "C" lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, co
     lbm_status s = check_ws(d_ws, ws_bytes, L.total, "lbm_cnn_gradients");
     if (s != LBM_OK) return s;
     char *ws = static_cast<char *>(d_ws);
-    s = gradients(d_params, batch, d_logk, d_target, d_pred, ws, L, stream);
+    s = gradients(d_params, batch, d_logk, d_sym, d_target, d_pred, ws, L, stream);
     if (s != LBM_OK) return s;
     if (d_grad)
         LBM_HIP(hipMemcpyAsync(d_grad, ws + L.off_grad, kNParams * 4, hipMemcpyDeviceToDevice, stream));
@@ -676,8 +755,9 @@ extern "C" lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, co
 }
 
 extern "C" lbm_status lbm_cnn_train_step(float *d_params, float *d_adam_m, float *d_adam_v, int32_t step, float lr,
-                                         int32_t batch, const float *d_logk, const float *d_target, float *d_loss,
-                                         void *d_ws, size_t ws_bytes, hipStream_t stream)
+                                         int32_t batch, const float *d_logk, const int8_t *d_sym,
+                                         const float *d_target, float *d_loss, void *d_ws, size_t ws_bytes,
+                                         hipStream_t stream)
 {
     if (batch < 1 || !d_params || !d_adam_m || !d_adam_v || !d_logk || !d_target || step < 1 || !(lr > 0.0f))
         return set_error(LBM_EINVAL, "lbm_cnn_train_step: bad argument");
@@ -686,7 +766,7 @@ extern "C" lbm_status lbm_cnn_train_step(float *d_params, float *d_adam_m, float
     if (s != LBM_OK) return s;
     char *ws = static_cast<char *>(d_ws);
     float *pred = reinterpret_cast<float *>(ws + L.off_pred);
-    s = gradients(d_params, batch, d_logk, d_target, pred, ws, L, stream);
+    s = gradients(d_params, batch, d_logk, d_sym, d_target, pred, ws, L, stream);
     if (s != LBM_OK) return s;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);

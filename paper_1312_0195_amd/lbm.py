@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_EDEVICE, LBM_ENOTCONV, LBM_ENONFINITE, LBM_EWORKSPACE = 0, -1, -2, -3, -4, -5
 LBM_F32_SHIFTED, LBM_F64 = 0, 1
 LBM_PERM_SCALAR, LBM_PERM_TENSOR = 1, 4
+LBM_SCHEME_SHAN_CHEN, LBM_SCHEME_GUO = 0, 1
 LBM_KEFF_SCALAR, LBM_KEFF_TENSOR = 0, 1
 
 #: every symbol the header declares (checked against include/lbm.h by the tests)
@@ -44,7 +45,8 @@ class lbm_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("eps", ctypes.c_double), ("nu", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("walls_y", ctypes.c_int32),
-                ("pop_dtype", ctypes.c_int32), ("perm_kind", ctypes.c_int32)]
+                ("pop_dtype", ctypes.c_int32), ("perm_kind", ctypes.c_int32),
+                ("scheme", ctypes.c_int32)]
 
 
 class lbm_local_params(ctypes.Structure):
@@ -117,13 +119,14 @@ def lib():
     L.lbm_cnn_param_count.restype = ctypes.c_int32
     L.lbm_cnn_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
     L.lbm_cnn_workspace_bytes.restype = ctypes.c_size_t
-    L.lbm_cnn_forward.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.lbm_cnn_forward.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, _vp,
+                                  ctypes.c_size_t, _vp]
     L.lbm_cnn_forward.restype = ctypes.c_int
-    L.lbm_cnn_gradients.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp,
+    L.lbm_cnn_gradients.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp]
     L.lbm_cnn_gradients.restype = ctypes.c_int
     L.lbm_cnn_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_int32,
-                                     _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+                                     _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.lbm_cnn_train_step.restype = ctypes.c_int
     L.lbm_status_str.argtypes = [ctypes.c_int]
     L.lbm_status_str.restype = ctypes.c_char_p
@@ -277,24 +280,25 @@ def lbm_cnn_workspace_bytes(batch: int, training: bool) -> int:
     return int(lib().lbm_cnn_workspace_bytes(int(batch), int(bool(training))))
 
 
-def lbm_cnn_forward(d_params, batch, d_logk, d_pred, d_stats, d_ws, ws_bytes, stream=None) -> None:
-    _raise(lib().lbm_cnn_forward(_ptr(d_params), int(batch), _ptr(d_logk), _ptr(d_pred),
+def lbm_cnn_forward(d_params, batch, d_logk, n_sym, d_pred, d_stats, d_ws, ws_bytes,
+                    stream=None) -> None:
+    _raise(lib().lbm_cnn_forward(_ptr(d_params), int(batch), _ptr(d_logk), int(n_sym), _ptr(d_pred),
                                  _ptr(d_stats), _ptr(d_ws), int(ws_bytes), _stream(stream)),
            "lbm_cnn_forward")
 
 
-def lbm_cnn_gradients(d_params, batch, d_logk, d_target, d_grad, d_loss, d_pred, d_ws, ws_bytes,
-                      stream=None) -> None:
-    _raise(lib().lbm_cnn_gradients(_ptr(d_params), int(batch), _ptr(d_logk), _ptr(d_target),
-                                   _ptr(d_grad), _ptr(d_loss), _ptr(d_pred), _ptr(d_ws),
-                                   int(ws_bytes), _stream(stream)), "lbm_cnn_gradients")
+def lbm_cnn_gradients(d_params, batch, d_logk, d_sym, d_target, d_grad, d_loss, d_pred, d_ws,
+                      ws_bytes, stream=None) -> None:
+    _raise(lib().lbm_cnn_gradients(_ptr(d_params), int(batch), _ptr(d_logk), _ptr(d_sym),
+                                   _ptr(d_target), _ptr(d_grad), _ptr(d_loss), _ptr(d_pred),
+                                   _ptr(d_ws), int(ws_bytes), _stream(stream)), "lbm_cnn_gradients")
 
 
-def lbm_cnn_train_step(d_params, d_m, d_v, step, lr, batch, d_logk, d_target, d_loss, d_ws,
+def lbm_cnn_train_step(d_params, d_m, d_v, step, lr, batch, d_logk, d_sym, d_target, d_loss, d_ws,
                        ws_bytes, stream=None) -> None:
     _raise(lib().lbm_cnn_train_step(_ptr(d_params), _ptr(d_m), _ptr(d_v), int(step), float(lr),
-                                    int(batch), _ptr(d_logk), _ptr(d_target), _ptr(d_loss),
-                                    _ptr(d_ws), int(ws_bytes), _stream(stream)),
+                                    int(batch), _ptr(d_logk), _ptr(d_sym), _ptr(d_target),
+                                    _ptr(d_loss), _ptr(d_ws), int(ws_bytes), _stream(stream)),
            "lbm_cnn_train_step")
 
 
@@ -304,9 +308,10 @@ def lbm_cnn_train_step(d_params, d_m, d_v, step, lr, batch, d_logk, d_target, d_
 
 
 def make_params(nx, ny, tau, eps, nu, rho0=1.0, gx=0.0, gy=0.0, walls_y=0,
-                pop_dtype=LBM_F32_SHIFTED, perm_kind=LBM_PERM_SCALAR) -> lbm_params:
+                pop_dtype=LBM_F32_SHIFTED, perm_kind=LBM_PERM_SCALAR,
+                scheme=LBM_SCHEME_SHAN_CHEN) -> lbm_params:
     return lbm_params(int(nx), int(ny), float(tau), float(eps), float(nu), float(rho0), float(gx),
-                      float(gy), int(walls_y), int(pop_dtype), int(perm_kind))
+                      float(gy), int(walls_y), int(pop_dtype), int(perm_kind), int(scheme))
 
 
 def _workspace(nbytes: int, device):

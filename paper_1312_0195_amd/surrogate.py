@@ -9,6 +9,8 @@ problems of Sec. 3 give through Eq. tensor-kappa. This module:
   lbm_local_keff on the GPU;
 * trains the network on the GPU with the library's own forward, backward and
   Adam kernels (lbm_cnn_train_step);
+* trains with a random symmetry of the square per patch (the kernel applies
+  it as it reads the patch) and predicts with the mean over all eight;
 * predicts with lbm_cnn_forward, flags patches whose statistics (standard
   deviation and lag-1 correlations of log K, computed by the same kernel) fall
   outside the ranges seen in training, and sends those to lbm_local_keff.
@@ -37,7 +39,8 @@ def init_params(seed: int = 0) -> np.ndarray:
     parts = [rng.standard_normal(9 * C) * np.sqrt(2.0 / 9), np.zeros(C)]
     for _ in range(3):
         parts += [rng.standard_normal(9 * C * C) * np.sqrt(2.0 / (9 * C)), np.zeros(C)]
-    parts += [rng.standard_normal(H * (C + 1)) * np.sqrt(2.0 / (C + 1)), np.zeros(H),
+    nz = C + 5  # pooled channels, mean(log K), four series/parallel features
+    parts += [rng.standard_normal(H * nz) * np.sqrt(2.0 / nz), np.zeros(H),
               rng.standard_normal(2 * H) * np.sqrt(1.0 / H), np.zeros(2)]
     v = np.concatenate(parts).astype(np.float32)
     assert v.size == L.lbm_cnn_param_count()
@@ -105,12 +108,21 @@ def training_set(n_patches: int, seed: int = 1, field_side: int = 256,
 # ---------------------------------------------------------------------------
 
 
+def detector_features(stats) -> np.ndarray:
+    """Features of the range detector from the kernel's per-patch statistics
+    (mean, std, lag-1 correlation along x, along y): std, both correlations,
+    and their difference (anisotropy, e.g. channels)."""
+    s = np.asarray(stats, dtype=np.float64)
+    return np.stack([s[:, 1], s[:, 2], s[:, 3], s[:, 2] - s[:, 3]], axis=1)
+
+
 @dataclass
 class Surrogate:
     params: np.ndarray
-    stat_lo: np.ndarray = field(default_factory=lambda: np.full(3, -np.inf))
-    stat_hi: np.ndarray = field(default_factory=lambda: np.full(3, np.inf))
+    stat_lo: np.ndarray = field(default_factory=lambda: np.full(4, -np.inf))
+    stat_hi: np.ndarray = field(default_factory=lambda: np.full(4, np.inf))
     history: list = field(default_factory=list)
+    n_sym: int = 8
 
     @classmethod
     def new(cls, seed: int = 0) -> "Surrogate":
@@ -118,7 +130,7 @@ class Surrogate:
 
     # -- training ----------------------------------------------------------
     def fit(self, logk, target, epochs=20, batch=256, lr=2e-3, lr_final=1e-4, seed=0,
-            device="cuda", verbose=False):
+            device="cuda", augment=True, verbose=False):
         import torch
         dev = torch.device(device)
         n = len(logk)
@@ -132,11 +144,14 @@ class Surrogate:
         loss = torch.empty(1, dtype=torch.float32, device=dev)
         rng = np.random.default_rng(seed)
         steps_per_epoch = n // batch
+        syms = torch.empty(steps_per_epoch * batch, dtype=torch.int8, device=dev)
         total = max(1, epochs * steps_per_epoch)
         step = 0
         t0 = time.perf_counter()
         for ep in range(epochs):
             perm = torch.as_tensor(rng.permutation(n)[:steps_per_epoch * batch]).to(dev)
+            if augment:
+                syms.copy_(torch.as_tensor(rng.integers(0, 8, len(syms), dtype=np.int8)))
             ep_loss = torch.zeros(1, dtype=torch.float32, device=dev)
             for i in range(steps_per_epoch):
                 idx = perm[i * batch:(i + 1) * batch]
@@ -145,7 +160,8 @@ class Surrogate:
                 step += 1
                 # cosine decay from lr to lr_final
                 cur = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * (step - 1) / total))
-                L.lbm_cnn_train_step(prm, m, v, step, cur, batch, xb, yb, loss, ws, nb)
+                sb = syms[i * batch:(i + 1) * batch] if augment else None
+                L.lbm_cnn_train_step(prm, m, v, step, cur, batch, xb, sb, yb, loss, ws, nb)
                 ep_loss += loss
             torch.cuda.synchronize(dev)
             mean_loss = float(ep_loss.item()) / max(1, steps_per_epoch)
@@ -154,17 +170,20 @@ class Surrogate:
                 print(f"epoch {ep + 1}/{epochs}: loss {mean_loss:.3e} "
                       f"({time.perf_counter() - t0:.1f} s)", flush=True)
         self.params = prm.cpu().numpy()
-        # training-distribution ranges of the patch statistics (std, rx, ry)
-        _, stats = self.predict(logk, device=device)
-        s = stats[:, 1:4]
+        # training-distribution ranges of the patch statistics
+        _, stats = self.predict(logk, device=device, n_sym=1)
+        s = detector_features(stats)
         lo, hi = np.quantile(s, 0.001, axis=0), np.quantile(s, 0.999, axis=0)
         pad = 0.05 * (hi - lo)
         self.stat_lo, self.stat_hi = lo - pad, hi + pad
         return self
 
     # -- inference ---------------------------------------------------------
-    def predict(self, logk, device="cuda", batch=65536, stream_ws=None):
-        """(pred [n, 2] log kxx, log kyy; stats [n, 4] mean, std, rx, ry)."""
+    def predict(self, logk, device="cuda", batch=65536, n_sym=None):
+        """(pred [n, 2] log kxx, log kyy; stats [n, 8] mean, std, rx, ry and
+        the four series/parallel features). n_sym: symmetries averaged
+        (default: the model's own setting)."""
+        n_sym = self.n_sym if n_sym is None else n_sym
         import torch
         dev = torch.device(device)
         logk = np.ascontiguousarray(logk, np.float32)
@@ -175,27 +194,27 @@ class Surrogate:
             xb = torch.as_tensor(logk[s:s + batch]).to(dev)
             b = len(xb)
             pred = torch.empty((b, 2), dtype=torch.float32, device=dev)
-            st = torch.empty((b, 4), dtype=torch.float32, device=dev)
+            st = torch.empty((b, 8), dtype=torch.float32, device=dev)
             nb = L.lbm_cnn_workspace_bytes(b, False)
             ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-            L.lbm_cnn_forward(prm, b, xb, pred, st, ws, nb)
+            L.lbm_cnn_forward(prm, b, xb, n_sym, pred, st, ws, nb)
             preds.append(pred.cpu().numpy())
             stats.append(st.cpu().numpy())
         return np.concatenate(preds).astype(np.float64), np.concatenate(stats).astype(np.float64)
 
     def in_range(self, stats) -> np.ndarray:
-        s = np.asarray(stats)[:, 1:4]
+        s = detector_features(stats)
         return ((s >= self.stat_lo) & (s <= self.stat_hi)).all(axis=1)
 
     def save(self, path):
         np.savez(path, params=self.params, stat_lo=self.stat_lo, stat_hi=self.stat_hi,
-                 history=np.asarray(self.history))
+                 history=np.asarray(self.history), n_sym=np.int32(self.n_sym))
 
     @classmethod
     def load(cls, path) -> "Surrogate":
         d = np.load(path)
         return cls(d["params"].astype(np.float32), d["stat_lo"], d["stat_hi"],
-                   list(d["history"]))
+                   list(d["history"]), int(d["n_sym"]) if "n_sym" in d else 8)
 
 
 def keff_with_fallback(model: Surrogate, kappa_big, x0, y0, device="cuda"):

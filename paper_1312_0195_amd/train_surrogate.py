@@ -61,7 +61,27 @@ def test_set(n_total=65536, frac_oor=0.1, seed=12345):
     return big, x0, y0, is_oor
 
 
-def evaluate(model: S.Surrogate, big, x0, y0, is_oor):
+def _forward_timed(model, X, n_sym):
+    """Device-resident forward of all patches: (pred, stats, seconds)."""
+    import torch
+    prm = torch.as_tensor(model.params).cuda()
+    n = X.shape[0]
+    pred = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    st = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(n, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_forward(prm, n, X, n_sym, pred, st, ws, nb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    L.lbm_cnn_forward(prm, n, X, n_sym, pred, st, ws, nb)
+    e1.record()
+    torch.cuda.synchronize()
+    return (pred.cpu().numpy().astype(np.float64), st.cpu().numpy().astype(np.float64),
+            e0.elapsed_time(e1) * 1e-3)
+
+
+def evaluate(model: S.Surrogate, big, x0, y0, is_oor, sweep_nsym=(1, 2, 4, 8)):
     import torch
     # LBM labels for every test patch (the judge), timed: the LBM-only path
     torch.cuda.synchronize()
@@ -72,22 +92,8 @@ def evaluate(model: S.Surrogate, big, x0, y0, is_oor):
     logk = np.stack([np.log(I.cut_patch(big, a, b, S.SIDE)) for a, b in zip(x0, y0)])
     # network alone (device-resident inputs, kernel time only)
     X = torch.as_tensor(logk.astype(np.float32)).cuda()
-    prm = torch.as_tensor(model.params).cuda()
     n = len(x0)
-    pred = torch.empty((n, 2), dtype=torch.float32, device="cuda")
-    st = torch.empty((n, 4), dtype=torch.float32, device="cuda")
-    nb = L.lbm_cnn_workspace_bytes(n, False)
-    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    L.lbm_cnn_forward(prm, n, X, pred, st, ws, nb)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    L.lbm_cnn_forward(prm, n, X, pred, st, ws, nb)
-    e1.record()
-    torch.cuda.synchronize()
-    t_net = e0.elapsed_time(e1) * 1e-3
-    p = pred.cpu().numpy().astype(np.float64)
-    stats = st.cpu().numpy().astype(np.float64)
+    p, stats, t_net = _forward_timed(model, X, model.n_sym)
     ok = model.in_range(stats)
     # network + fallback for the flagged patches
     torch.cuda.synchronize()
@@ -104,19 +110,29 @@ def evaluate(model: S.Surrogate, big, x0, y0, is_oor):
     err = np.abs(np.expm1(p[inr] - y_lbm[inr]))  # relative K_eff error
     geo = np.abs(np.expm1(stats[inr, 0][:, None] - y_lbm[inr]))
     err_all = np.abs(np.expm1(combined[good] - y_lbm[good]))
+    acc_oor = ok & is_oor & good
+    err_acc_oor = np.abs(np.expm1(p[acc_oor] - y_lbm[acc_oor])) if acc_oor.any() else np.zeros(1)
 
     def q(a):
         return dict(p50=float(np.quantile(a, 0.5)), p95=float(np.quantile(a, 0.95)),
                     p99=float(np.quantile(a, 0.99)), max=float(a.max()))
 
+    # accuracy and speed against the number of symmetries averaged
+    sweep = {}
+    for ns in sweep_nsym:
+        pn, _, tn = _forward_timed(model, X, ns)
+        sweep[str(ns)] = dict(q(np.abs(np.expm1(pn[inr] - y_lbm[inr]))), patches_per_s=n / tn)
+
     return dict(
-        n_patches=int(n), n_true_oor=int(is_oor.sum()),
+        n_patches=int(n), n_true_oor=int(is_oor.sum()), n_sym=int(model.n_sym),
+        keff_error_in_range_by_n_sym=sweep,
         flagged=int((~ok).sum()), flagged_true_oor=int((~ok & is_oor).sum()),
         flagged_in_range=int((~ok & ~is_oor).sum()),
         lbm_label_failures=int((~good).sum()),
         keff_error_network_in_range=q(err),
         keff_error_geometric_mean_in_range=q(geo),
         keff_error_combined_all=q(err_all),
+        keff_error_network_accepted_out_of_range=q(err_acc_oor),
         seconds_lbm_only=t_lbm, seconds_network=t_net, seconds_fallback=t_fb,
         patches_per_s_lbm_only=n / t_lbm,
         patches_per_s_network=n / t_net,

@@ -98,3 +98,60 @@ def test_forward_flop_count():
     # 2 * 1024 * 9 * (32 + 3 * 32 * 32) + MLP = 57.2 MFLOP per 32 x 32 patch
     f = C.flops_forward()
     assert 57.1e6 < f < 57.3e6
+
+
+def test_series_parallel_features_of_layered_patch():
+    """Layers constant along x: flow along the layers sees the arithmetic mean
+    of the layer values, flow across them the harmonic mean (both estimates of
+    each pair coincide for a layered medium)."""
+    rng = np.random.default_rng(11)
+    layers = rng.normal(0.0, 1.0, 8)
+    x = np.repeat(layers[:, None], 5, axis=1)[None]  # [1, 8 rows, 5 columns]
+    k = np.exp(layers)
+    f = C.series_parallel(x)[0]
+    assert np.allclose(f[:2], np.log(k.mean()), rtol=0, atol=1e-13)
+    assert np.allclose(f[2:], -np.log(np.mean(1.0 / k)), rtol=0, atol=1e-13)
+
+
+def test_series_parallel_lower_estimate_below_upper():
+    """The mean of harmonic means never exceeds the harmonic mean of the
+    arithmetic means (concavity of the harmonic mean), in either direction."""
+    rng = np.random.default_rng(12)
+    f = C.series_parallel(rng.normal(0.0, 1.5, (20, 9, 7)))
+    assert (f[:, 0] <= f[:, 1] + 1e-14).all() and (f[:, 2] <= f[:, 3] + 1e-14).all()
+    assert (f[:, 1] - f[:, 0] > 1e-3).all()
+
+
+def test_transform_matches_pixel_loops_and_forms_the_group():
+    rng = np.random.default_rng(13)
+    a = rng.standard_normal((1, 4, 4))
+    seen = set()
+    for s in range(8):
+        t = C.transform(a, s)
+        for y in range(4):
+            for x in range(4):
+                u, v = (y, x) if s & 1 else (x, y)
+                if s & 2:
+                    u = 3 - u
+                if s & 4:
+                    v = 3 - v
+                assert t[0, y, x] == a[0, v, u]
+        seen.add(t.tobytes())
+    assert len(seen) == 8
+
+
+def test_symmetric_prediction_is_equivariant():
+    """Averaging over the whole group makes the prediction equivariant: a
+    transformed patch gets the same K_eff, with kxx and kyy exchanged when the
+    symmetry transposes."""
+    p = C.init_params(C=4, hidden=6, seed=3)
+    rng = np.random.default_rng(14)
+    x = rng.standard_normal((2, 6, 6))
+    y = C.predict_symmetric(p, x)
+    for s in range(8):
+        ys = C.predict_symmetric(p, C.transform(x, s))
+        assert np.allclose(ys, y[:, ::-1] if s & 1 else y, rtol=1e-12, atol=1e-13)
+    # one evaluation alone is not (a generic network breaks the symmetry)
+    y1 = C.predict_symmetric(p, x, n_sym=1)
+    y1t = C.predict_symmetric(p, C.transform(x, 1), n_sym=1)
+    assert np.abs(y1t[:, ::-1] - y1).max() > 1e-6

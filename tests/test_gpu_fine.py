@@ -25,8 +25,9 @@ def L():
     return lbm
 
 
-def _gpu_run(L, nx, ny, kappa, tau, eps, nu, g, walls, steps, dtype, force=None, perm_kind=1):
-    p = L.make_params(nx, ny, tau, eps, nu, 1.0, g[0], g[1], walls, dtype, perm_kind)
+def _gpu_run(L, nx, ny, kappa, tau, eps, nu, g, walls, steps, dtype, force=None, perm_kind=1,
+             scheme=0):
+    p = L.make_params(nx, ny, tau, eps, nu, 1.0, g[0], g[1], walls, dtype, perm_kind, scheme)
     s = L.FineSolver(p, kappa, force)
     st, done, mu = s.step(steps)
     assert st == L.LBM_OK and done == steps
@@ -35,8 +36,9 @@ def _gpu_run(L, nx, ny, kappa, tau, eps, nu, g, walls, steps, dtype, force=None,
     return out
 
 
-def _oracle_run(nx, ny, kappa, tau, eps, nu, g, walls, steps, force=None, perm_kind=1):
-    p = O.Params(nx=nx, ny=ny, tau=tau, eps=eps, nu=nu, walls_y=walls, perm_kind=perm_kind)
+def _oracle_run(nx, ny, kappa, tau, eps, nu, g, walls, steps, force=None, perm_kind=1, scheme=0):
+    p = O.Params(nx=nx, ny=ny, tau=tau, eps=eps, nu=nu, walls_y=walls, perm_kind=perm_kind,
+                 scheme=scheme)
     r = O.run(p, kappa, g, max_steps=steps, force=force)
     rho, ux, uy = O.moments(p, kappa, r.f, g, force)
     return np.stack([ux, uy]), rho, r
@@ -94,6 +96,37 @@ def test_fine_tensor_and_force_field(L, dtype):
     dt = L.LBM_F64 if dtype == "f64" else L.LBM_F32_SHIFTED
     u_g, _, _, _ = _gpu_run(L, nx, ny, kt, 0.7, 0.5, 0.1, (0, 0), 0, 200, dt, force, 4)
     assert _rel_field_err(u_g, u_o) < (1e-9 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("nx,ny,walls,tau,with_force", [(64, 64, 1, 0.8, False), (300, 7, 0, 0.53, True),
+                                                       (37, 23, 1, 0.5, True)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_guo_form_matches_oracle_guo_form(L, nx, ny, walls, tau, with_force, dtype):
+    """The Guo form (Sec. 2.1) on the GPU against the oracle's own Guo form."""
+    k = I.lognormal_kappa(nx, ny, 1.2, 4.0, seed=13)
+    force = 1e-6 * np.random.default_rng(3).standard_normal((ny, nx, 2)) if with_force else None
+    g = (1e-6, 2e-7)
+    u_o, rho_o, _ = _oracle_run(nx, ny, k, tau, 0.4, 0.1, g, walls, 200, force, 1, 1)
+    dt = L.LBM_F64 if dtype == "f64" else L.LBM_F32_SHIFTED
+    u_g, rho_g, _, _ = _gpu_run(L, nx, ny, k, tau, 0.4, 0.1, g, walls, 200, dt, force, 1, 1)
+    assert _rel_field_err(u_g, u_o) < (1e-9 if dtype == "f64" else 1e-5)
+    assert np.max(np.abs(rho_g - rho_o)) < (1e-13 if dtype == "f64" else 1e-9)
+
+
+def test_guo_form_equals_shan_chen_form_on_gpu(L):
+    """With the linear f_eq the two forms are algebraically equal (Sec. 2.1 vs
+    2.2): FP64 populations agree to rounding after 300 steps."""
+    nx, ny = 96, 40
+    k = I.lognormal_kappa(nx, ny, 1.5, 6.0, seed=14)
+    _, _, _, a = _gpu_run(L, nx, ny, k, 0.7, 0.4, 0.1, (1e-6, 3e-7), 1, 300, L.LBM_F64)
+    _, _, _, b = _gpu_run(L, nx, ny, k, 0.7, 0.4, 0.1, (1e-6, 3e-7), 1, 300, L.LBM_F64, None, 1, 1)
+    fa, fb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+    ja = fa[1] - fa[3]
+    assert np.max(np.abs(fa - fb)) < 1e-9 * np.max(np.abs(ja))
+    with pytest.raises(L.LbmError):
+        L.FineSolver(L.make_params(8, 8, 0.7, 0.4, 0.1, 1.0, 1e-6, 0.0, 0, L.LBM_F64,
+                                   L.LBM_PERM_TENSOR, L.LBM_SCHEME_GUO),
+                     np.broadcast_to([1.0, 0.0, 0.0, 1.0], (8, 8, 4)).copy())
 
 
 def test_fine_converges_to_oracle_steady_state(L):

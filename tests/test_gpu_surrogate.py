@@ -60,7 +60,7 @@ def _patches(n, seed):
 
 def test_param_count_matches_layout(L):
     p = _params(0)
-    assert L.lbm_cnn_param_count() == _flat(p).size == 29218
+    assert L.lbm_cnn_param_count() == _flat(p).size == 29346
 
 
 @pytest.mark.parametrize("batch", [1, 7, 300])
@@ -72,10 +72,10 @@ def test_forward_matches_oracle(L, batch):
     prm = torch.tensor(_flat(p), device="cuda")
     xd = torch.tensor(x.astype(np.float32), device="cuda")
     pred = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
-    stats = torch.empty((batch, 4), dtype=torch.float32, device="cuda")
+    stats = torch.empty((batch, 8), dtype=torch.float32, device="cuda")
     nb = L.lbm_cnn_workspace_bytes(batch, False)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    L.lbm_cnn_forward(prm, batch, xd, pred, stats, ws, nb)
+    L.lbm_cnn_forward(prm, batch, xd, 1, pred, stats, ws, nb)
     torch.cuda.synchronize()
     pred = pred.cpu().numpy().astype(np.float64)
     err = np.abs(pred - pred_o)
@@ -89,6 +89,47 @@ def test_forward_matches_oracle(L, batch):
     rx = (xc * np.roll(xc, -1, axis=2)).mean(axis=(1, 2)) / sd ** 2
     ry = (xc * np.roll(xc, -1, axis=1)).mean(axis=(1, 2)) / sd ** 2
     assert np.allclose(st[:, 2], rx, atol=1e-4) and np.allclose(st[:, 3], ry, atol=1e-4)
+    # series/parallel features (FP32 exp and sums of 32 terms)
+    assert np.allclose(st[:, 4:], C.series_parallel(xc), rtol=0, atol=2e-5)
+
+
+@pytest.mark.parametrize("n_sym", [2, 5, 8])
+def test_symmetric_forward_matches_oracle(L, n_sym):
+    p = _params(11)
+    x = _patches(37, 12)
+    pred_o = C.predict_symmetric(p, x, n_sym)
+    prm = torch.tensor(_flat(p), device="cuda")
+    xd = torch.tensor(x.astype(np.float32), device="cuda")
+    pred = torch.empty((37, 2), dtype=torch.float32, device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(37, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_forward(prm, 37, xd, n_sym, pred, None, ws, nb)
+    err = np.abs(pred.cpu().numpy() - pred_o)
+    assert err.max() < 2e-2 * (1 + np.abs(pred_o).max()), err.max()
+    assert np.sqrt((err ** 2).sum() / (pred_o ** 2).sum()) < 5e-3
+
+
+def test_symmetric_forward_is_equivariant_on_gpu(L):
+    """With all eight symmetries averaged, a transformed patch reads exactly the
+    same eight pixel arrangements as the original, so predictions agree up to
+    the FP32 order of the average, with kxx and kyy exchanged by a transpose."""
+    p = _params(13)
+    x = _patches(3, 14)
+    prm = torch.tensor(_flat(p), device="cuda")
+    allx = np.concatenate([C.transform(x, s) for s in range(8)])
+    xd = torch.tensor(allx.astype(np.float32), device="cuda")
+    pred = torch.empty((24, 2), dtype=torch.float32, device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(24, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_forward(prm, 24, xd, 8, pred, None, ws, nb)
+    pr = pred.cpu().numpy().reshape(8, 3, 2)
+    for s in range(8):
+        want = pr[0][:, ::-1] if s & 1 else pr[0]
+        assert np.allclose(pr[s], want, rtol=0, atol=1e-5), s
+    with pytest.raises(L.LbmError):
+        L.lbm_cnn_forward(prm, 24, xd, 9, pred, None, ws, nb)
+    with pytest.raises(L.LbmError):
+        L.lbm_cnn_forward(prm, 24, xd, 0, pred, None, ws, nb)
 
 
 def test_forward_shift_invariance_on_gpu(L):
@@ -100,7 +141,7 @@ def test_forward_shift_invariance_on_gpu(L):
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     both = torch.tensor(np.concatenate([x, xs]).astype(np.float32), device="cuda")
     pred = torch.empty((8, 2), dtype=torch.float32, device="cuda")
-    L.lbm_cnn_forward(prm, 8, both, pred, None, ws, nb)
+    L.lbm_cnn_forward(prm, 8, both, 1, pred, None, ws, nb)
     pr = pred.cpu().numpy()
     # Invariant in exact arithmetic. On the GPU the patch mean (and the pooled
     # sums) are added in a different pixel order after a shift, which can move
@@ -108,26 +149,36 @@ def test_forward_shift_invariance_on_gpu(L):
     assert np.allclose(pr[:4], pr[4:], rtol=0, atol=1e-4)
 
 
-@pytest.mark.parametrize("batch", [3, 64])
-def test_gradients_match_oracle(L, batch):
+@pytest.mark.parametrize("batch,with_sym", [(3, False), (64, False), (40, True)])
+def test_gradients_match_oracle(L, batch, with_sym):
+    """With per-patch symmetries the oracle sees the transformed patches and
+    the targets exchanged for the transposed ones."""
     p = _params(4)
     x = _patches(batch, 6)
     rng = np.random.default_rng(7)
     t = x.mean(axis=(1, 2))[:, None] + rng.normal(0.3, 0.5, (batch, 2))
-    y_o, cache = C.forward(p, x)
-    g_o = C.backward(p, cache, y_o, t - cache["m"][:, None])
-    loss_o = C.loss(y_o, t - cache["m"][:, None])
+    sym = rng.integers(0, 8, batch).astype(np.int8) if with_sym else np.zeros(batch, np.int8)
+    xo = np.stack([C.transform(x[i:i + 1], int(sym[i]))[0] for i in range(batch)])
+    to = np.where((sym & 1)[:, None] == 1, t[:, ::-1], t)
+    y_o, cache = C.forward(p, xo)
+    g_o = C.backward(p, cache, y_o, to - cache["m"][:, None])
+    loss_o = C.loss(y_o, to - cache["m"][:, None])
     prm = torch.tensor(_flat(p), device="cuda")
     xd = torch.tensor(x.astype(np.float32), device="cuda")
+    sd = torch.tensor(sym, device="cuda") if with_sym else None
     td = torch.tensor(t.astype(np.float32), device="cuda")
     grad = torch.empty_like(prm)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     pred = torch.empty((batch, 2), dtype=torch.float32, device="cuda")
     nb = L.lbm_cnn_workspace_bytes(batch, True)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    L.lbm_cnn_gradients(prm, batch, xd, td, grad, loss, pred, ws, nb)
+    L.lbm_cnn_gradients(prm, batch, xd, sd, td, grad, loss, pred, ws, nb)
     torch.cuda.synchronize()
     assert abs(float(loss.item()) - loss_o) < 2e-2 * loss_o
+    po = y_o + cache["m"][:, None]
+    po = np.where((sym & 1)[:, None] == 1, po[:, ::-1], po)  # back to the patch's own axes
+    pe = np.abs(pred.cpu().numpy() - po)
+    assert pe.max() < 2e-2 * (1 + np.abs(y_o).max())
     g = _unflat(grad.cpu().numpy(), p)
     for k in NAMES:
         a, b = g[k].ravel(), g_o[k].ravel()
@@ -136,7 +187,7 @@ def test_gradients_match_oracle(L, batch):
         assert cos > 0.999 and rel < 3e-2, (k, cos, rel)
     # deterministic: the same call gives the same bits
     grad2 = torch.empty_like(prm)
-    L.lbm_cnn_gradients(prm, batch, xd, td, grad2, loss, pred, ws, nb)
+    L.lbm_cnn_gradients(prm, batch, xd, sd, td, grad2, loss, pred, ws, nb)
     assert torch.equal(grad, grad2)
 
 
@@ -153,10 +204,11 @@ def test_adam_step_matches_oracle(L):
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     grad = torch.empty_like(prm)
     pred = torch.empty((16, 2), dtype=torch.float32, device="cuda")
-    L.lbm_cnn_gradients(prm, 16, xd, td, grad, None, pred, ws, nb)
+    sd = torch.tensor(np.arange(16, dtype=np.int8) % 8, device="cuda")
+    L.lbm_cnn_gradients(prm, 16, xd, sd, td, grad, None, pred, ws, nb)
     g = grad.cpu().numpy().astype(np.float64)
     before = prm.cpu().numpy().astype(np.float64)
-    L.lbm_cnn_train_step(prm, m, v, 1, 1e-3, 16, xd, td, None, ws, nb)
+    L.lbm_cnn_train_step(prm, m, v, 1, 1e-3, 16, xd, sd, td, None, ws, nb)
     torch.cuda.synchronize()
     ref = {"w": before.copy()}
     C.adam_step(ref, {"w": g}, {}, lr=1e-3)

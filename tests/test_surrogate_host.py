@@ -1,0 +1,48 @@
+"""Host-side pieces of the surrogate: parameter layout, the committed model,
+the range detector and the patch mosaic (no GPU)."""
+import os
+
+import numpy as np
+
+from oracle import cnn_oracle as C
+from paper_1312_0195_amd import inputs as I
+from paper_1312_0195_amd import lbm as L
+from paper_1312_0195_amd import surrogate as S
+from paper_1312_0195_amd import train_surrogate as T
+
+
+def test_parameter_count_matches_the_oracle_layout():
+    p = C.init_params(C=32, hidden=32)
+    assert L.lbm_cnn_param_count() == sum(v.size for v in p.values())
+    assert S.init_params().size == L.lbm_cnn_param_count()
+
+
+def test_committed_model_loads():
+    assert os.path.exists(T.DEFAULT_MODEL)
+    m = S.Surrogate.load(T.DEFAULT_MODEL)
+    assert m.params.dtype == np.float32 and m.params.size == L.lbm_cnn_param_count()
+    assert np.isfinite(m.params).all()
+    assert (m.stat_lo < m.stat_hi).all() and len(m.history) > 0
+
+
+def test_range_detector():
+    m = S.Surrogate(S.init_params(), np.array([0.5, 0.8, 0.8, -0.05]),
+                    np.array([3.0, 1.0, 1.0, 0.05]))
+    stats = np.array([[0.0, 1.0, 0.9, 0.9],     # inside
+                      [0.0, 3.5, 0.9, 0.9],     # std too large
+                      [0.0, 1.0, 0.99, 0.85]])  # anisotropic
+    assert list(m.in_range(stats)) == [True, False, False]
+
+
+def test_mosaic_keeps_fields_and_tiles():
+    fields = [np.full((64, 64), i + 1.0) for i in range(5)]
+    big, x0, y0 = S.mosaic(fields)
+    assert len(x0) == 5 * 4
+    for i, (a, b) in enumerate(zip(x0, y0)):
+        patch = I.cut_patch(big, a, b, 32)
+        assert (patch == i // 4 + 1).all()
+
+
+def test_test_set_mix():
+    big, x0, y0, oor = T.test_set(n_total=64 * 20, frac_oor=0.1, seed=3)
+    assert len(x0) == 64 * 20 and oor.sum() == 128
