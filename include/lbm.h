@@ -149,6 +149,10 @@ typedef struct {
     double tol;           /* relative change of the mean velocity between checks */
     int32_t check_every;  /* steps between checks, even and >= 2 */
     int64_t max_steps;    /* per-item cap (rounded up to a multiple of check_every) */
+    int32_t pop_dtype;    /* LBM_F32_SHIFTED: FP32 state and arithmetic (fast);
+                             LBM_F64: FP64 state and arithmetic, needed where a
+                             step moves the state by less than half an FP32
+                             ulp (tau near 1/2 with weak drag) */
 } lbm_local_params;
 
 /* One row of the tile table: how items of side `side` are laid out on a
@@ -176,7 +180,9 @@ size_t lbm_local_workspace_bytes(int32_t n_patches);
  * d_flags: device int32 [n_patches][2]: 0 converged, 1 step cap reached,
  *          2 non-finite, -1 drive skipped (or NULL).
  * tiles/n_tiles: optional tile table (NULL/0 for the built-in one).
- * block_threads: workgroup size, 256, 512 or 1024 (0 for 1024).
+ * block_threads: workgroup size, 256, 512 or 1024 (0 for 1024); FP64 items
+ *          run with at most 512 (tile rows asking for more are ignored), so
+ *          their sides are limited to side^2 <= 4 x 512.
  * Asynchronous; the host arrays may be reused when the call returns. */
 lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patches, const int32_t *h_x0,
                           const int32_t *h_y0, const int32_t *h_side, const int32_t *h_drive_mask,

@@ -12,8 +12,12 @@
 //    runs one item. Items of one side share a launch-wide tile choice (G per
 //    side) and run side by side, so small patches still fill the CU.
 //  * Populations 1..8 of an item live in LDS (8 planes of side^2 FP32
-//    deviations, 32 B per cell); the rest population and the drag coefficient
-//    stay in registers of the thread that owns the cell.
+//    deviations, 32 B per cell, or FP64 with 64 B per cell); the rest
+//    population and the drag coefficient stay in registers of the thread that
+//    owns the cell. FP32 items use FP32 arithmetic; FP64 items FP64 throughout,
+//    for regimes where a step changes the state by less than half an FP32 ulp
+//    (tau near 1/2 with weak drag: FP32 state then stops short of the fixed
+//    point).
 //  * Streaming in place ("AA" order): on even steps a cell reads its own
 //    slots and writes the post-collision values back reversed
 //    (A[opp(a)][x] = f*_a); on odd steps it reads f_a from A[opp(a)][x - e_a]
@@ -68,6 +72,7 @@ struct LocalArgs {
     int *__restrict__ flags_out;
     float om, omc, twotau, omtt;         // 1/tau, 1 - 1/tau, 2 tau, 1 - 2 tau
     float heg;                           // eps g / 2
+    double om_d, omc_d, twotau_d, omtt_d;
     double heg_d;
     double h;                            // eps nu / 2
     double nu_over_g;
@@ -78,26 +83,42 @@ struct LocalArgs {
 
 __device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Relaxation constants in the arithmetic type P.
+template <typename P> struct Consts;
+template <> struct Consts<float> {
+    float om, omc, twotau, omtt, heg;
+    __device__ explicit Consts(const struct LocalArgs &a);
+};
+template <> struct Consts<double> {
+    double om, omc, twotau, omtt, heg;
+    __device__ explicit Consts(const struct LocalArgs &a);
+};
+__device__ inline Consts<float>::Consts(const LocalArgs &a)
+    : om(a.om), omc(a.omc), twotau(a.twotau), omtt(a.omtt), heg(a.heg) {}
+__device__ inline Consts<double>::Consts(const LocalArgs &a)
+    : om(a.om_d), omc(a.omc_d), twotau(a.twotau_d), omtt(a.omtt_d), heg(a.heg_d) {}
+
 // One collision of a cell in deviation form (see lbm_fine.hip for the
 // derivation): f[0..8] in, post-collision values out in f.
-__device__ __forceinline__ void collide(float f[9], float D, float hegx, float hegy, const LocalArgs &a)
+template <typename P>
+__device__ __forceinline__ void collide(P f[9], P D, P hegx, P hegy, const Consts<P> &k)
 {
-    const float dr = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const float jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
-    const float jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
-    const float rho = 1.0f + dr;
-    const float tD = a.twotau * D;
-    const float mx = tD * (jx + hegx * rho) + a.omtt * jx;
-    const float my = tD * (jy + hegy * rho) + a.omtt * jy;
-    const float om = a.om, omc = a.omc;
-    const float s0 = (4.0f / 9.0f) * om * dr;
-    const float b = (1.0f / 9.0f) * om * dr;
-    const float bx = (1.0f / 3.0f) * om * mx;
-    const float by = (1.0f / 3.0f) * om * my;
-    const float cc = (1.0f / 36.0f) * om * dr;
-    const float cx = (1.0f / 12.0f) * om * mx;
-    const float cy = (1.0f / 12.0f) * om * my;
-    const float pp = cx + cy, qq = cx - cy;
+    const P dr = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const P jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+    const P jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    const P rho = P(1) + dr;
+    const P tD = k.twotau * D;
+    const P mx = tD * (jx + hegx * rho) + k.omtt * jx;
+    const P my = tD * (jy + hegy * rho) + k.omtt * jy;
+    const P om = k.om, omc = k.omc;
+    const P s0 = (P(4) / P(9)) * om * dr;
+    const P b = (P(1) / P(9)) * om * dr;
+    const P bx = (P(1) / P(3)) * om * mx;
+    const P by = (P(1) / P(3)) * om * my;
+    const P cc = (P(1) / P(36)) * om * dr;
+    const P cx = (P(1) / P(12)) * om * mx;
+    const P cy = (P(1) / P(12)) * om * my;
+    const P pp = cx + cy, qq = cx - cy;
     f[0] = omc * f[0] + s0;
     f[1] = omc * f[1] + (b + bx);
     f[2] = omc * f[2] + (b + by);
@@ -109,10 +130,12 @@ __device__ __forceinline__ void collide(float f[9], float D, float hegx, float h
     f[8] = omc * f[8] + (cc + qq);
 }
 
-template <int T>
+template <int T, typename P>
 __global__ __launch_bounds__(T) void k_local(LocalArgs a)
 {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    P *lds = reinterpret_cast<P *>(lds_raw);
+    const Consts<P> kc(a);
     constexpr int NW = T / 64;
     __shared__ double red[NW][2];
     __shared__ int ctrl[NW];  // item index per slot (at most NW slots), -1 = none
@@ -126,10 +149,10 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
     bool have_prev = false;
     double prev_x = 0.0, prev_y = 0.0;
     int out = 0, x0 = 0, y0 = 0;
-    float hegx = 0.0f, hegy = 0.0f;
+    P hegx = 0, hegy = 0;
     double hegx_d = 0.0, hegy_d = 0.0;
     // per-cell registers
-    float f0[kCPT], Dc[kCPT];
+    P f0[kCPT], Dc[kCPT];
     int xy[kCPT];
 
     bool need_item = true;
@@ -141,7 +164,7 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
         const int S2 = S * S;
         const int slot = tid / G, lt = tid - slot * G;
         const bool in_slot = slot < cd.nslots;
-        float *A = lds + (size_t)(in_slot ? slot : 0) * 8 * S2;
+        P *A = lds + (size_t)(in_slot ? slot : 0) * 8 * S2;
 
         // ---- control: claim items for slots that need one -------------------
         if (in_slot && lt == 0 && need_item) {
@@ -158,8 +181,8 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
                 y0 = it.y;
                 out = it.w;
                 const int drive = out & 1;
-                hegx = drive == 0 ? a.heg : 0.0f;
-                hegy = drive == 1 ? a.heg : 0.0f;
+                hegx = drive == 0 ? kc.heg : P(0);
+                hegy = drive == 1 ? kc.heg : P(0);
                 hegx_d = drive == 0 ? a.heg_d : 0.0;
                 hegy_d = drive == 1 ? a.heg_d : 0.0;
                 steps = 0;
@@ -173,10 +196,11 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
                         const int fx = (x0 + x) % a.fnx, fy = (y0 + y) % a.fny;
                         const double kap = a.field[(size_t)fy * a.fnx + fx];
                         // kappa <= 0 or NaN poisons the item: it ends flagged non-finite
-                        Dc[k] = (kap > 0.0) ? (float)(1.0 / (1.0 + a.h / kap)) : __int_as_float(0x7fc00000);
-                        f0[k] = 0.0f;
+                        Dc[k] = (kap > 0.0) ? (P)(1.0 / (1.0 + a.h / kap))
+                                            : (P)__longlong_as_double(0x7ff8000000000000LL);
+                        f0[k] = P(0);
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) A[q * S2 + c] = 0.0f;
+                        for (int q = 0; q < 8; ++q) A[q * S2 + c] = P(0);
                     }
                 }
             }
@@ -203,13 +227,13 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
                     const int c = lt + k * G;
                     if (k < C && c < S2) {
                         const int x = xy[k] & 255, y = xy[k] >> 8;
-                        float f[9];
+                        P f[9];
                         f[0] = f0[k];
                         if (!odd) {
                             // own slots, in order; written back reversed
 #pragma unroll
                             for (int q = 1; q < 9; ++q) f[q] = A[(q - 1) * S2 + c];
-                            collide(f, Dc[k], hegx, hegy, a);
+                            collide<P>(f, Dc[k], hegx, hegy, kc);
                             A[(3 - 1) * S2 + c] = f[1];
                             A[(4 - 1) * S2 + c] = f[2];
                             A[(1 - 1) * S2 + c] = f[3];
@@ -231,7 +255,7 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
                             f[6] = A[(8 - 1) * S2 + rm + xp];
                             f[7] = A[(5 - 1) * S2 + rp + xp];
                             f[8] = A[(6 - 1) * S2 + rp + xm];
-                            collide(f, Dc[k], hegx, hegy, a);
+                            collide<P>(f, Dc[k], hegx, hegy, kc);
                             // f*_a goes to A[a][x + e_a]
                             A[(1 - 1) * S2 + r0 + xp] = f[1];
                             A[(2 - 1) * S2 + rp + x] = f[2];
@@ -365,17 +389,17 @@ int pow2_at_least(int v)
     return p;
 }
 
-template <int T>
+template <int T, typename P>
 lbm_status launch_local(const LocalArgs &a, size_t lds_bytes, int grid, hipStream_t stream)
 {
     if (lds_bytes > 64 * 1024)
-        LBM_HIP(hipFuncSetAttribute((const void *)k_local<T>,
+        LBM_HIP(hipFuncSetAttribute((const void *)k_local<T, P>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     int occ = 0;
-    LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_local<T>, T, lds_bytes));
+    LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_local<T, P>, T, lds_bytes));
     if (occ < 1) return set_error(LBM_EINVAL, "lbm_local_keff: tile does not fit on a CU");
     const int blocks = std::min(grid, device_cu_count() * occ);
-    hipLaunchKernelGGL(k_local<T>, dim3(blocks), dim3(T), lds_bytes, stream, a);
+    hipLaunchKernelGGL((k_local<T, P>), dim3(blocks), dim3(T), lds_bytes, stream, a);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -412,6 +436,8 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
         return set_error(LBM_EINVAL, std::string(fn) + "check_every must be even and >= 2");
     if (lp->max_steps < 1 || lp->max_steps > (int64_t)1 << 30)
         return set_error(LBM_EINVAL, std::string(fn) + "max_steps must lie in [1, 2^30]");
+    if (lp->pop_dtype != LBM_F32_SHIFTED && lp->pop_dtype != LBM_F64)
+        return set_error(LBM_EINVAL, std::string(fn) + "unknown pop_dtype");
     if (n_patches < 0) return set_error(LBM_EINVAL, std::string(fn) + "n_patches < 0");
     if (n_patches == 0) return LBM_OK;
     if (!h_x0 || !h_y0 || !h_side || !h_drive_mask || !d_kappa_field || !d_keff)
@@ -439,7 +465,10 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     std::vector<int4> items;
     items.reserve(2 * (size_t)n_patches);
     std::vector<ClassDesc> classes;
-    const int T = block_threads;
+    const bool f64 = lp->pop_dtype == LBM_F64;
+    // FP64 state needs twice the registers: at most 512 threads per workgroup
+    const int T = f64 ? std::min(block_threads, 512) : block_threads;
+    const size_t cb = f64 ? 64 : 32;  // LDS bytes per cell (populations 1..8)
     const int budget = lds_budget_bytes() - 2048;
     size_t lds_max = 0;
     for (int i : order) {
@@ -450,11 +479,11 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
             c.begin = (int)items.size();
             int G = 0;
             for (int t = 0; t < n_tiles; ++t)
-                if (tiles[t].side == s) G = tiles[t].slot_threads;
+                if (tiles[t].side == s && !(f64 && tiles[t].slot_threads > T)) G = tiles[t].slot_threads;
             const int cells = s * s;
             if (G == 0) {
                 const int gmin = pow2_at_least((cells + kCPT - 1) / kCPT);
-                const int fit = std::max(1, budget / (32 * cells));
+                const int fit = std::max(1, budget / (int)(cb * cells));
                 G = std::max(gmin, pow2_at_least((T + fit - 1) / fit));
                 G = std::min(G, T);
             }
@@ -463,14 +492,14 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
             c.slot_threads = G;
             c.cells_per_thread = (cells + G - 1) / G;
             if (c.cells_per_thread > kCPT)
-                return set_error(LBM_EINVAL, std::string(fn) + "tile leaves more than 8 cells per thread (side " +
+                return set_error(LBM_EINVAL, std::string(fn) + "tile leaves more than 4 cells per thread (side " +
                                                      std::to_string(s) + ")");
             c.nslots = T / G;
-            while (c.nslots > 1 && (size_t)c.nslots * 32 * cells > (size_t)budget) --c.nslots;
-            if ((size_t)32 * cells > (size_t)budget)
+            while (c.nslots > 1 && (size_t)c.nslots * cb * cells > (size_t)budget) --c.nslots;
+            if (cb * cells > (size_t)budget)
                 return set_error(LBM_EINVAL, std::string(fn) + "patch of side " + std::to_string(s) +
                                                      " does not fit in LDS");
-            lds_max = std::max(lds_max, (size_t)c.nslots * 32 * cells);
+            lds_max = std::max(lds_max, (size_t)c.nslots * cb * cells);
             classes.push_back(c);
         }
         for (int d = 0; d < 2; ++d)
@@ -518,6 +547,10 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     a.omtt = (float)(1.0 - 2.0 * lp->tau);
     a.heg = (float)(0.5 * lp->eps * lp->g);
     a.heg_d = 0.5 * lp->eps * lp->g;
+    a.om_d = 1.0 / lp->tau;
+    a.omc_d = 1.0 - 1.0 / lp->tau;
+    a.twotau_d = 2.0 * lp->tau;
+    a.omtt_d = 1.0 - 2.0 * lp->tau;
     a.h = 0.5 * lp->eps * lp->nu;
     a.nu_over_g = lp->nu / lp->g;
     a.tol = lp->tol;
@@ -528,9 +561,13 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     int need = 0;
     for (const ClassDesc &c : classes) need = std::max(need, (c.count + c.nslots - 1) / c.nslots);
     const int grid = std::max(1, need);
+    if (f64) {
+        if (T == 256) return launch_local<256, double>(a, lds_max, grid, stream);
+        return launch_local<512, double>(a, lds_max, grid, stream);
+    }
     switch (T) {
-    case 256: return launch_local<256>(a, lds_max, grid, stream);
-    case 512: return launch_local<512>(a, lds_max, grid, stream);
-    default: return launch_local<1024>(a, lds_max, grid, stream);
+    case 256: return launch_local<256, float>(a, lds_max, grid, stream);
+    case 512: return launch_local<512, float>(a, lds_max, grid, stream);
+    default: return launch_local<1024, float>(a, lds_max, grid, stream);
     }
 }

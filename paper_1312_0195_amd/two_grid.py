@@ -59,12 +59,15 @@ def setting(case: str, n: int = 400):
                 nu=U.nu(NU_PHYS), units=U, k_const_lat=float(U.kappa(c["k_const"])))
 
 
-def local_keff(kappa_dev, tau, nu, tol=1e-10, max_steps=4_000_000):
-    """K* tensor of every R x R subdomain (fine lattice units) [nc, nc, 4]."""
+def local_keff(kappa_dev, tau, nu, tol=1e-10, max_steps=8_000_000):
+    """K* tensor of every R x R subdomain (fine lattice units) [nc, nc, 4].
+    FP64 state: with tau near 1/2 and weak drag (the Brinkman case) a step
+    changes the state by less than half an FP32 ulp long before the fixed
+    point, and an FP32 state stalls short of it."""
     n = kappa_dev.shape[0]
     x0, y0, side = I.tile_patches(n, n, R)
     res = L.local_keff(None, x0, y0, side, tau, EPS, nu, 1e-6, tol=tol, check_every=200,
-                       max_steps=max_steps, kappa_dev=kappa_dev)
+                       max_steps=max_steps, kappa_dev=kappa_dev, pop_dtype=L.LBM_F64)
     nc = n // R
     return res.keff.reshape(nc, nc, 4), res.flags.reshape(nc, nc, 2), res.steps.reshape(nc, nc, 2)
 

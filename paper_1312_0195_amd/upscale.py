@@ -10,6 +10,12 @@
 
 The comparison metric is the relative L2 difference of the velocity fields on
 the coarse grid. Every step runs in the HIP library; torch holds the buffers.
+
+    python -m paper_1312_0195_amd.upscale [--n 4096] [--r 64] [--channels]
+
+runs the upscaling workload (log-normal K, sigma 2, correlation length
+64 n / 4096, periodic; optionally with high-permeability streaks) and prints
+the timings and errors as one JSON line.
 """
 from __future__ import annotations
 
@@ -55,7 +61,7 @@ def local_tensor(kappa_dev, r, tau, eps, nu, g, tol=1e-7):
 
 
 def coarse_solve(kappa_shape, keff, r, tau, eps, nu, g, mode, tol=1e-7, max_steps=4_000_000,
-                 pop_dtype=None):
+                 pop_dtype=None, check_every=100):
     import torch
     ny, nx = kappa_shape
     ncy, ncx = keff.shape[:2]
@@ -65,17 +71,32 @@ def coarse_solve(kappa_shape, keff, r, tau, eps, nu, g, mode, tol=1e-7, max_step
     u = torch.empty((2, ncy, ncx), dtype=torch.float64, device="cuda")
     nb = L.lbm_coarse_workspace_bytes(ncx, ncy)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    st, steps = L.lbm_coarse_solve(fine, r, kd, mode, None, max_steps, tol, 100, u, None, ws, nb)
+    st, steps = L.lbm_coarse_solve(fine, r, kd, mode, None, max_steps, tol, check_every, u, None,
+                                   ws, nb)
     return u.cpu().numpy(), steps, st
 
 
-def fine_solve(kappa, tau, eps, nu, g, tol=1e-7, max_steps=2_000_000, check_every=1000):
-    """Fine-grid velocity at steady state (periodic), [2, ny, nx] on device."""
+def fine_solve(kappa, tau, eps, nu, g, tol=1e-7, max_steps=2_000_000, check_every=1000,
+               chunk=None, verbose=False):
+    """Fine-grid velocity at steady state (periodic), [2, ny, nx] on device.
+    With chunk set, runs in calls of that many steps (a multiple of
+    check_every; the solver keeps its last check across calls) and prints
+    progress after each."""
     import torch
     ny, nx = kappa.shape
     p = L.make_params(nx, ny, tau, eps, nu, 1.0, g, 0.0, 0, L.LBM_F32_SHIFTED)
     s = L.FineSolver(p, kappa)
-    st, steps, _ = s.step(max_steps, tol, check_every)
+    chunk = max_steps if chunk is None else chunk
+    steps, st = 0, L.LBM_ENOTCONV
+    t0 = time.perf_counter()
+    while steps < max_steps:
+        st, done, mu = s.step(min(chunk, max_steps - steps), tol, check_every)
+        steps += done
+        if verbose:
+            print(f"fine: {steps} steps, mean u {mu[0]:.9e} {mu[1]:.9e}, "
+                  f"{time.perf_counter() - t0:.1f} s", flush=True)
+        if st != L.LBM_ENOTCONV:
+            break
     u = torch.empty((2, ny, nx), dtype=torch.float64, device="cuda")
     L.lbm_fields(s.h, u, None)
     return u, steps, st, s
@@ -91,7 +112,8 @@ def block_average(u_dev, r):
 
 
 def run(kappa, r, tau=0.8, eps=0.4, nu=0.1, g=1e-6, fine_tol=1e-7, fine_max_steps=2_000_000,
-        fine_check=1000, coarse_tol=1e-7) -> UpscaleResult:
+        fine_check=1000, coarse_tol=1e-7, verbose=False, coarse_check=100,
+        coarse_max_steps=4_000_000) -> UpscaleResult:
     import torch
     kd = torch.as_tensor(np.ascontiguousarray(kappa)).cuda()
     torch.cuda.synchronize()
@@ -100,16 +122,58 @@ def run(kappa, r, tau=0.8, eps=0.4, nu=0.1, g=1e-6, fine_tol=1e-7, fine_max_step
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     u_c, c_steps, _ = coarse_solve(kappa.shape, keff, r, tau, eps, nu, g, L.LBM_KEFF_TENSOR,
-                                   coarse_tol)
+                                   coarse_tol, coarse_max_steps, check_every=coarse_check)
     t2 = time.perf_counter()
-    u_cs, _, _ = coarse_solve(kappa.shape, keff, r, tau, eps, nu, g, L.LBM_KEFF_SCALAR, coarse_tol)
+    u_cs, _, _ = coarse_solve(kappa.shape, keff, r, tau, eps, nu, g, L.LBM_KEFF_SCALAR, coarse_tol,
+                              coarse_max_steps, check_every=coarse_check)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
+    if verbose:
+        print(f"local problems {t1 - t0:.2f} s, coarse solves {t3 - t1:.2f} s", flush=True)
     u_f, f_steps, f_st, solver = fine_solve(kappa, tau, eps, nu, g, fine_tol, fine_max_steps,
-                                            fine_check)
+                                            fine_check,
+                                            chunk=fine_check * max(1, 20000 // fine_check)
+                                            if verbose else None, verbose=verbose)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     u_avg = block_average(u_f, r)
     solver.close()
     return UpscaleResult(keff, u_c, u_avg, _rel_l2(u_c, u_avg), _rel_l2(u_cs, u_avg),
                          t1 - t0, t2 - t1, t4 - t3, f_steps, f_st, c_steps, ok)
+
+
+def main():
+    import argparse
+    import json
+    from . import inputs as I
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--r", type=int, default=64)
+    ap.add_argument("--channels", action="store_true")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-6,
+                    help="relative change allowed per check on both grids")
+    ap.add_argument("--coarse-check", type=int, default=100,
+                    help="coarse steps between checks; the fine grid checks every r times "
+                         "as many steps, the same physical time")
+    ap.add_argument("--fine-max-steps", type=int, default=2_000_000)
+    args = ap.parse_args()
+    L.lib()
+    w = I.workload_upscale(seed=args.seed, n=args.n, channels=args.channels)
+    res = run(w["kappa"], args.r, fine_tol=args.tol, fine_check=args.coarse_check * args.r,
+              fine_max_steps=args.fine_max_steps, coarse_tol=args.tol,
+              coarse_check=args.coarse_check, verbose=True)
+    print(json.dumps(dict(
+        n=args.n, r=args.r, channels=args.channels, seed=args.seed,
+        rel_l2_tensor=res.rel_l2, rel_l2_scalar=res.rel_l2_scalar,
+        t_local_s=res.t_local, t_coarse_s=res.t_coarse, t_fine_s=res.t_fine,
+        speedup_upscaled_vs_fine=res.t_fine / (res.t_local + res.t_coarse),
+        fine_steps=res.fine_steps, fine_status=res.fine_status, coarse_steps=res.coarse_steps,
+        tol=args.tol, coarse_check=args.coarse_check, fine_check=args.coarse_check * args.r,
+        local_flags_ok=res.local_flags_ok,
+        max_abs_kxy_over_kxx=float(np.max(np.abs(res.keff[..., 1]) / res.keff[..., 0])))),
+        flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -141,3 +141,32 @@ def test_local_full_size_sampled(L):
     # every tensor is positive on the diagonal and finite
     assert np.isfinite(rt.keff).all() and (rt.keff[:, [0, 3]] > 0).all()
     assert np.isfinite(rm.keff).all() and (rm.keff[:, [0, 3]] > 0).all()
+
+
+def test_local_f64_state_reaches_fixed_point_where_f32_stalls(L):
+    """FP64 populations (pop_dtype LBM_F64) against the exact fixed point, at
+    tight tolerance, on mixed sides up to 40 (ragged slots). Also the regime
+    that needs them: a uniform patch at tau 0.50012 with weak drag, whose
+    exact K_eff is kappa (closed form of the uniform transient). There the
+    FP32 state stops changing while still short of the fixed point."""
+    field = I.lognormal_kappa(96, 96, 1.5, 6.0, seed=4)
+    x0 = np.array([0, 50, 7, 80], np.int32)
+    y0 = np.array([0, 11, 60, 90], np.int32)
+    s = np.array([40, 24, 13, 8], np.int32)
+    r = L.local_keff(field, x0, y0, s, TAU, EPS, NU, G, tol=1e-11, max_steps=2_000_000,
+                     pop_dtype=L.LBM_F64)
+    assert (r.flags == 0).all()
+    for i in range(4):
+        ko = DS.keff_direct(I.cut_patch(field, x0[i], y0[i], s[i]), TAU, EPS, NU, G)
+        scale = max(abs(ko[0]), abs(ko[3]))
+        assert np.max(np.abs(r.keff[i] - ko)) / scale < 1e-7
+    # uniform patch, tau 0.50012, nu 8e-6, kappa 0.016: drag eps nu / 2 kappa = 2e-4
+    kap = np.full((10, 10), 0.016)
+    one = np.zeros(1, np.int32)
+    r64 = L.local_keff(kap, one, one, np.array([10], np.int32), 0.50012, 0.8, 8e-6, 1e-6,
+                       tol=1e-12, check_every=200, max_steps=4_000_000, pop_dtype=L.LBM_F64)
+    assert (r64.flags == 0).all()
+    assert np.allclose(r64.keff[0, [0, 3]], 0.016, rtol=1e-8)
+    with pytest.raises(L.LbmError):   # side 48 does not fit 4 cells per thread at 512 threads
+        L.local_keff(field, one, one, np.array([48], np.int32), TAU, EPS, NU, G,
+                     pop_dtype=L.LBM_F64)
