@@ -87,16 +87,23 @@ def label_patches(kappa_big, x0, y0, tol=1e-7, chunk=65536, device="cuda"):
     return out, flags
 
 
-def training_set(n_patches: int, seed: int = 1, field_side: int = 256,
-                 sigma_range=(0.5, 2.5), corr_range=(4.0, 32.0)):
-    """(log K patches [n, 32, 32] FP32, targets [n, 2]) from fields with sigma
-    and correlation length drawn uniformly from the given ranges."""
+def training_patches(n_patches: int, seed: int = 1, field_side: int = 256,
+                     sigma_range=(0.5, 2.5), corr_range=(4.0, 32.0)):
+    """(kappa mosaic, x0, y0) of the training tiles: fields with sigma and
+    correlation length drawn uniformly from the given ranges."""
     per = (field_side // SIDE) ** 2
     n_fields = -(-n_patches // per)
     fields = [f for _, _, f in I.surrogate_fields(n_fields, seed, field_side, sigma_range,
                                                      corr_range)]
     big, x0, y0 = mosaic(fields)
-    x0, y0 = x0[:n_patches], y0[:n_patches]
+    return big, x0[:n_patches], y0[:n_patches]
+
+
+def training_set(n_patches: int, seed: int = 1, field_side: int = 256,
+                 sigma_range=(0.5, 2.5), corr_range=(4.0, 32.0)):
+    """(log K patches [n, 32, 32] FP32, targets [n, 2]) of training_patches,
+    labelled by the batched LBM (patches whose LBM run fails are dropped)."""
+    big, x0, y0 = training_patches(n_patches, seed, field_side, sigma_range, corr_range)
     y, flags = label_patches(big, x0, y0)
     ok = (flags == 0).all(axis=1)
     logk = np.stack([np.log(I.cut_patch(big, a, b, SIDE)) for a, b in zip(x0, y0)])
@@ -110,17 +117,23 @@ def training_set(n_patches: int, seed: int = 1, field_side: int = 256,
 
 def detector_features(stats) -> np.ndarray:
     """Features of the range detector from the kernel's per-patch statistics
-    (mean, std, lag-1 correlation along x, along y): std, both correlations,
-    and their difference (anisotropy, e.g. channels)."""
+    (mean, std, lag-1 correlation along x, along y, then the series/parallel
+    estimates sx_lo, sx_up, sy_lo, sy_up): std, both correlations, their
+    difference (anisotropy, e.g. channels), and when present the gap between
+    the upper and lower estimate in each direction (contrast and its
+    connectivity) and the difference of the two upper estimates."""
     s = np.asarray(stats, dtype=np.float64)
-    return np.stack([s[:, 1], s[:, 2], s[:, 3], s[:, 2] - s[:, 3]], axis=1)
+    cols = [s[:, 1], s[:, 2], s[:, 3], s[:, 2] - s[:, 3]]
+    if s.shape[1] >= 8:
+        cols += [s[:, 5] - s[:, 4], s[:, 7] - s[:, 6], s[:, 5] - s[:, 7]]
+    return np.stack(cols, axis=1)
 
 
 @dataclass
 class Surrogate:
     params: np.ndarray
-    stat_lo: np.ndarray = field(default_factory=lambda: np.full(4, -np.inf))
-    stat_hi: np.ndarray = field(default_factory=lambda: np.full(4, np.inf))
+    stat_lo: np.ndarray = field(default_factory=lambda: np.full(7, -np.inf))
+    stat_hi: np.ndarray = field(default_factory=lambda: np.full(7, np.inf))
     history: list = field(default_factory=list)
     n_sym: int = 8
 
@@ -170,12 +183,16 @@ class Surrogate:
                 print(f"epoch {ep + 1}/{epochs}: loss {mean_loss:.3e} "
                       f"({time.perf_counter() - t0:.1f} s)", flush=True)
         self.params = prm.cpu().numpy()
-        # training-distribution ranges of the patch statistics
+        self.calibrate(logk, device=device)
+        return self
+
+    def calibrate(self, logk, q=0.001, pad=0.05, device="cuda"):
+        """Range detector: per feature, the [q, 1 - q] quantiles over the
+        training patches, widened by pad times their spread."""
         _, stats = self.predict(logk, device=device, n_sym=1)
         s = detector_features(stats)
-        lo, hi = np.quantile(s, 0.001, axis=0), np.quantile(s, 0.999, axis=0)
-        pad = 0.05 * (hi - lo)
-        self.stat_lo, self.stat_hi = lo - pad, hi + pad
+        lo, hi = np.quantile(s, q, axis=0), np.quantile(s, 1.0 - q, axis=0)
+        self.stat_lo, self.stat_hi = lo - pad * (hi - lo), hi + pad * (hi - lo)
         return self
 
     # -- inference ---------------------------------------------------------
@@ -203,7 +220,7 @@ class Surrogate:
         return np.concatenate(preds).astype(np.float64), np.concatenate(stats).astype(np.float64)
 
     def in_range(self, stats) -> np.ndarray:
-        s = detector_features(stats)
+        s = detector_features(stats)[:, :len(self.stat_lo)]
         return ((s >= self.stat_lo) & (s <= self.stat_hi)).all(axis=1)
 
     def save(self, path):

@@ -56,8 +56,9 @@ def test_set(n_total=65536, frac_oor=0.1, seed=12345):
         else:
             oor.append(I.channelize(I.lognormal_kappa(256, 256, 1.0, 8.0, s), 0.25, 8, 1e3, s))
     big, x0, y0 = S.mosaic(fields + oor)
-    is_oor = np.zeros(len(x0), bool)
-    is_oor[n_in_fields * per:] = True
+    is_oor = np.zeros(len(x0), np.int8)  # 0 in range; 1, 2, 3: the three kinds above
+    for i in range(n_oor_fields):
+        is_oor[(n_in_fields + i) * per:(n_in_fields + i + 1) * per] = 1 + i % 3
     return big, x0, y0, is_oor
 
 
@@ -83,6 +84,8 @@ def _forward_timed(model, X, n_sym):
 
 def evaluate(model: S.Surrogate, big, x0, y0, is_oor, sweep_nsym=(1, 2, 4, 8)):
     import torch
+    kind = np.asarray(is_oor).astype(np.int8)
+    is_oor = kind > 0
     # LBM labels for every test patch (the judge), timed: the LBM-only path
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -123,8 +126,18 @@ def evaluate(model: S.Surrogate, big, x0, y0, is_oor, sweep_nsym=(1, 2, 4, 8)):
         pn, _, tn = _forward_timed(model, X, ns)
         sweep[str(ns)] = dict(q(np.abs(np.expm1(pn[inr] - y_lbm[inr]))), patches_per_s=n / tn)
 
+    by_kind = {}
+    for kk, nm in ((1, "sigma3.5_l8"), (2, "sigma1_l1.5"), (3, "streaks")):
+        m = (kind == kk) & good
+        if m.any():
+            acc = m & ok
+            e = np.abs(np.expm1(p[acc] - y_lbm[acc])) if acc.any() else np.zeros(1)
+            by_kind[nm] = dict(n=int(m.sum()), flagged=int((m & ~ok).sum()),
+                               accepted_err_p50=float(np.quantile(e, 0.5)),
+                               accepted_err_p95=float(np.quantile(e, 0.95)))
     return dict(
         n_patches=int(n), n_true_oor=int(is_oor.sum()), n_sym=int(model.n_sym),
+        out_of_range_by_kind=by_kind,
         keff_error_in_range_by_n_sym=sweep,
         flagged=int((~ok).sum()), flagged_true_oor=int((~ok & is_oor).sum()),
         flagged_in_range=int((~ok & ~is_oor).sum()),
@@ -149,9 +162,25 @@ def main():
     ap.add_argument("--test", type=int, default=65536)
     ap.add_argument("--model", default=DEFAULT_MODEL)
     ap.add_argument("--results", default=None)
+    ap.add_argument("--recalibrate", action="store_true",
+                    help="keep the trained weights of --model, recompute the range detector "
+                         "from the (regenerated, unlabelled) training patches, and evaluate")
     args = ap.parse_args()
     import torch
     L.lib()
+    if args.recalibrate:
+        model = S.Surrogate.load(args.model)
+        big, x0, y0 = S.training_patches(args.train, seed=1)
+        logk = np.stack([np.log(I.cut_patch(big, a, b, S.SIDE)) for a, b in zip(x0, y0)])
+        model.calibrate(logk.astype(np.float32))
+        model.save(args.model)
+        bt, xt, yt, is_oor = test_set(args.test)
+        res = evaluate(model, bt, xt, yt, is_oor)
+        print(json.dumps(res), flush=True)
+        if args.results:
+            with open(args.results, "w") as fh:
+                json.dump(res, fh, indent=1)
+        return
     t0 = time.perf_counter()
     X, Y = S.training_set(args.train, seed=1)
     t_data = time.perf_counter() - t0

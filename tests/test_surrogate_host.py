@@ -45,4 +45,17 @@ def test_mosaic_keeps_fields_and_tiles():
 
 def test_test_set_mix():
     big, x0, y0, oor = T.test_set(n_total=64 * 20, frac_oor=0.1, seed=3)
-    assert len(x0) == 64 * 20 and oor.sum() == 128
+    assert len(x0) == 64 * 20 and (oor > 0).sum() == 128
+    assert set(np.unique(oor[oor > 0])) == {1, 2}  # two out-of-range fields: kinds 1 and 2
+
+
+def test_detector_uses_series_parallel_gaps():
+    """With the eight-column statistics the detector also bounds the gap
+    between the upper and lower series/parallel estimates."""
+    st = np.array([[0.0, 1.0, 0.9, 0.9, -0.3, 0.3, -0.3, 0.3],
+                   [0.0, 1.0, 0.9, 0.9, -2.0, 2.0, -0.3, 0.3]])
+    f = S.detector_features(st)
+    assert f.shape == (2, 7) and np.allclose(f[:, 4], [0.6, 4.0])
+    m = S.Surrogate(S.init_params(), np.array([0.5, 0.8, 0.8, -0.05, 0.0, 0.0, -1.0]),
+                    np.array([3.0, 1.0, 1.0, 0.05, 1.0, 1.0, 1.0]))
+    assert list(m.in_range(st)) == [True, False]
