@@ -59,6 +59,49 @@ struct StepArgs {
     double hegx_d, hegy_d, om_d, omc_d, twotau_d, omtt_d, rho0_d;
 };
 
+// Plane accessors: element i of plane q of an SoA array with a plane stride.
+// GMem indexes through a 64-bit pointer per lane. BMem goes through a buffer
+// resource per plane, built in scalar registers from the (uniform) plane base,
+// so a lane only supplies a 32-bit byte offset: this removes the 64-bit
+// address arithmetic from the VALU. An offset past the plane reads zero and a
+// store there is dropped (the hardware bounds check of raw buffer accesses).
+// Plane bytes stay below 2^31 (the grid-size limit of params_ok).
+template <typename R>
+struct GMem {
+    const R *p;
+    R *w;
+    int stride;
+    __device__ R ld(int q, int i) const { return p[(size_t)q * stride + i]; }
+    __device__ void st(int q, int i, R v) const { w[(size_t)q * stride + i] = v; }
+};
+
+template <typename R>
+struct BMem {
+    const R *p;
+    R *w;
+    int stride;
+    static constexpr int kFlags = 0x00020000;  // gfx9 dword 3: 32-bit data format
+    __device__ R ld(int q, int i) const
+    {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(p + (size_t)q * stride), 0, stride * (int)sizeof(R), kFlags);
+        if constexpr (sizeof(R) == 4)
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
+        else
+            return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, 0));
+    }
+    __device__ void st(int q, int i, R v) const
+    {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(w + (size_t)q * stride), 0, stride * (int)sizeof(R), kFlags);
+        if constexpr (sizeof(R) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, i * 4, 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(
+                __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, i * 8, 0, 0);
+    }
+};
+
 // Pull the nine pre-collision deviations of cell (x, y): f_a(x) = f*_a(x - e_a)
 // from the previous step, with periodic wrap in x (and in y without walls)
 // and halfway bounce-back f_a(x) = f*_opp(a)(x) where x - e_a is beyond a wall.
@@ -103,6 +146,38 @@ __device__ __forceinline__ void pull(const R *__restrict__ fin, int stride, int 
     }
 }
 
+// pull through a plane accessor (same indices as pull)
+template <typename R, bool WALLS, class M>
+__device__ __forceinline__ void pullm(const M &in, int nx, int ny, int x, int y, R f[9])
+{
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const int rc = y * nx;
+    f[0] = in.ld(0, rc + x);
+    f[1] = in.ld(1, rc + xm);
+    f[3] = in.ld(3, rc + xp);
+    if (WALLS) {
+        const bool lo = (y == 0), hi = (y == ny - 1);
+        const int rm = (lo ? y : y - 1) * nx;
+        const int rp = (hi ? y : y + 1) * nx;
+        f[2] = lo ? in.ld(4, rc + x) : in.ld(2, rm + x);
+        f[5] = lo ? in.ld(7, rc + x) : in.ld(5, rm + xm);
+        f[6] = lo ? in.ld(8, rc + x) : in.ld(6, rm + xp);
+        f[4] = hi ? in.ld(2, rc + x) : in.ld(4, rp + x);
+        f[7] = hi ? in.ld(5, rc + x) : in.ld(7, rp + xp);
+        f[8] = hi ? in.ld(6, rc + x) : in.ld(8, rp + xm);
+    } else {
+        const int rm = ((y == 0) ? ny - 1 : y - 1) * nx;
+        const int rp = ((y == ny - 1) ? 0 : y + 1) * nx;
+        f[2] = in.ld(2, rm + x);
+        f[5] = in.ld(5, rm + xm);
+        f[6] = in.ld(6, rm + xp);
+        f[4] = in.ld(4, rp + x);
+        f[7] = in.ld(7, rp + xp);
+        f[8] = in.ld(8, rp + xm);
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void moments(const R f[9], R &dr, R &jx, R &jy)
 {
@@ -129,21 +204,22 @@ __device__ __forceinline__ int xcd_block(int bid, int nb)
 // forms: u from Eq. explicit-u-in-Guo (one division), the drag force f_m of
 // Eq. f_m-depends-on-u, f_eq at u (Eq. feq), the forcing term F_a of Eq.
 // Fi-of-Guo and the update of Eq. f-evolution-of-Guo. coef holds eps nu / kappa.
-template <typename R, bool FF>
+template <typename R, bool FF, class M>
 __device__ __forceinline__ void collide_cell_guo(const StepArgs<R> &a, double f[9], int c)
 {
+    const M cm{a.coef, nullptr, a.cstride}, fm{a.hforce, nullptr, a.cstride};
     double dr, jx, jy;
     moments(f, dr, jx, jy);
     const double rho = a.rho0_d + dr;
     double hgx, hgy;  // eps G / 2
     if (FF) {
-        hgx = (double)a.hforce[c];
-        hgy = (double)a.hforce[a.cstride + c];
+        hgx = (double)fm.ld(0, c);
+        hgy = (double)fm.ld(1, c);
     } else {
         hgx = a.hegx_d;
         hgy = a.hegy_d;
     }
-    const double cnu = (double)a.coef[c];
+    const double cnu = (double)cm.ld(0, c);
     const double den = rho * (1.0 + 0.5 * cnu);
     const double ux = (jx + hgx * rho) / den, uy = (jy + hgy * rho) / den;
     // rho f_m = rho (eps G - (eps nu / kappa) u)
@@ -166,32 +242,33 @@ __device__ __forceinline__ void collide_cell_guo(const StepArgs<R> &a, double f[
 
 // PK: 1 scalar drag coefficient D, 4 tensor M (Shan-Chen form); 0 the Guo
 // form with coef = eps nu / kappa.
-template <typename R, int PK, bool FF>
+template <typename R, int PK, bool FF, class M = GMem<R>>
 __device__ __forceinline__ void collide_cell(const StepArgs<R> &a, double f[9], int c)
 {
     if (PK == 0) {
-        collide_cell_guo<R, FF>(a, f, c);
+        collide_cell_guo<R, FF, M>(a, f, c);
         return;
     }
+    const M cm{a.coef, nullptr, a.cstride}, fm{a.hforce, nullptr, a.cstride};
     double dr, jx, jy;
     moments(f, dr, jx, jy);
     const double rho = a.rho0_d + dr;
     double hx, hy;
     if (FF) {
-        hx = jx + (double)a.hforce[c] * rho;
-        hy = jy + (double)a.hforce[a.cstride + c] * rho;
+        hx = jx + (double)fm.ld(0, c) * rho;
+        hy = jy + (double)fm.ld(1, c) * rho;
     } else {
         hx = jx + a.hegx_d * rho;
         hy = jy + a.hegy_d * rho;
     }
     double mx, my;  // rho u_eq
     if (PK == 1) {
-        const double tD = a.twotau_d * (double)a.coef[c];
+        const double tD = a.twotau_d * (double)cm.ld(0, c);
         mx = tD * hx + a.omtt_d * jx;
         my = tD * hy + a.omtt_d * jy;
     } else {
-        const double m00 = a.coef[c], m01 = a.coef[a.cstride + c];
-        const double m10 = a.coef[2 * a.cstride + c], m11 = a.coef[3 * a.cstride + c];
+        const double m00 = cm.ld(0, c), m01 = cm.ld(1, c);
+        const double m10 = cm.ld(2, c), m11 = cm.ld(3, c);
         mx = a.twotau_d * (m00 * hx + m01 * hy) + a.omtt_d * jx;
         my = a.twotau_d * (m10 * hx + m11 * hy) + a.omtt_d * jy;
     }
@@ -242,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
 
 // Tile of the two-step kernel: TX x TY output cells per workgroup.
 template <typename R> struct Tile2;
-template <> struct Tile2<float> { static constexpr int TX = 64, TY = 32, BS = 512; };
+template <> struct Tile2<float> { static constexpr int TX = 64, TY = 64, BS = 1024; };
 template <> struct Tile2<double> { static constexpr int TX = 32, TY = 16, BS = 256; };
 
 // Two time steps per launch (temporal blocking). Phase 1 takes step t on the
@@ -263,7 +340,7 @@ __global__ __launch_bounds__(Tile2<R>::BS) void k_step2(StepArgs<R> a)
     const int bid = xcd_block(blockIdx.x, gridDim.x);
     const int y0 = (bid / ntx) * TY, x0 = (bid % ntx) * TX;
     const int tw = min(TX, nx - x0), th = min(TY, ny - y0);  // ragged tiles at the far edges
-    const size_t S = (size_t)a.stride;
+    const BMem<R> mem{a.fin, a.fout, a.stride};
     for (int i = threadIdx.x; i < HN; i += BS) {
         const int hx = i % HX, hy = i / HX;
         if (hx > tw + 1 || hy > th + 1) continue;
@@ -276,11 +353,11 @@ __global__ __launch_bounds__(Tile2<R>::BS) void k_step2(StepArgs<R> a)
             y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
         }
         R fr[9];
-        pull<R, WALLS>(a.fin, a.stride, nx, ny, x, y, fr);
+        pullm<R, WALLS>(mem, nx, ny, x, y, fr);
         double f[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) f[q] = (double)fr[q];
-        collide_cell<R, PK, FF>(a, f, y * nx + x);
+        collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
 #pragma unroll
         for (int q = 0; q < 9; ++q) h[q][i] = (R)f[q];
     }
@@ -302,9 +379,9 @@ __global__ __launch_bounds__(Tile2<R>::BS) void k_step2(StepArgs<R> a)
         f[7] = (double)(hi ? h[5][c] : h[7][c + HX + 1]);
         f[8] = (double)(hi ? h[6][c] : h[8][c + HX - 1]);
         const int g = y * nx + x;
-        collide_cell<R, PK, FF>(a, f, g);
+        collide_cell<R, PK, FF, BMem<R>>(a, f, g);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) a.fout[q * S + g] = (R)f[q];
+        for (int q = 0; q < 9; ++q) mem.st(q, g, (R)f[q]);
     }
 }
 
