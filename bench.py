@@ -34,9 +34,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D2Q9 Brinkman, % HBM roofline); K_eff patches/s surrogate vs LBM @2%"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 (FMA)
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions per second (one per 4 cycles per SIMD)
 BYTES_PER_LU = 76  # per cell and launch: 9 x 4 B read + 9 x 4 B written + 4 B drag coefficient
+FLOPS_PER_LU = 65  # FP64 operations of one collision as the kernel writes it (FMA = 2)
+DEPTH = 6          # time steps per launch of the fine-step kernel (FP32 state)
 STEP_KERNEL_SRC = os.path.join(ROOT, "paper_1312_0195_amd", "csrc", "lbm_fine.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fine_step_2048_hbm_counters.md")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "fine_step_2048_valu_counters.md")
 
 
 def _src_hash(path):
@@ -44,17 +49,27 @@ def _src_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def _traffic_per_launch():
-    """HBM bytes per step-kernel launch from the committed counter summary,
-    or None when it is missing or was taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def _summary_value(path, pattern):
+    """A number from a committed counter summary, or None when the summary is
+    missing or was taken on a different kernel source."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_SUMMARY).read()
+    txt = open(path).read()
     m_src = re.search(r"kernel source sha256\[:16\]:\s*([0-9a-f]{16})", txt)
-    m_b = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
+    m_b = re.search(pattern, txt)
     if not m_src or not m_b or m_src.group(1) != _src_hash(STEP_KERNEL_SRC):
         return None
     return float(m_b.group(1))
+
+
+def _traffic_per_launch():
+    """HBM bytes per step-kernel launch (scaled FETCH_SIZE + WRITE_SIZE)."""
+    return _summary_value(TRAFFIC_SUMMARY, r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)")
+
+
+def _valu_per_launch():
+    """Wave64 VALU instructions per step-kernel launch (SQ_INSTS_VALU)."""
+    return _summary_value(VALU_SUMMARY, r"SQ_INSTS_VALU per launch:\s*([0-9.eE+]+)")
 
 
 def bench_fine(L, torch, kappa, steps, warmup, check_every=100):
@@ -75,15 +90,15 @@ def bench_fine(L, torch, kappa, steps, warmup, check_every=100):
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     assert st == L.LBM_OK and done == steps and np.isfinite(mu).all()
-    # step kernel alone: back-to-back launches of the two-step kernel, no
-    # reductions, same stream (k even: k / 2 launches)
-    k = max(2, min(steps, 2000) // 2 * 2)
+    # step kernel alone: back-to-back launches of the multi-step kernel, no
+    # reductions, same stream (k a multiple of DEPTH: k / DEPTH launches)
+    k = max(DEPTH, min(steps, 2400) // DEPTH * DEPTH)
     e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e2.record(stream)
     s.step(k, 0.0, 0)
     e3.record(stream)
     torch.cuda.synchronize()
-    step_ms = e2.elapsed_time(e3) / (k // 2)  # per launch (two time steps)
+    step_ms = e2.elapsed_time(e3) / (k // DEPTH)  # per launch (DEPTH time steps)
     s.close()
     return dict(wall_s=wall, event_ms=ev_ms, step_kernel_ms=step_ms, mean_u=mu.tolist())
 
@@ -186,8 +201,8 @@ def main():
                     help="also run a plain 302 MB device copy, the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -212,11 +227,15 @@ def main():
     fine = bench_fine(L, torch, kappa, args.steps, args.warmup)
     ms_per_step = fine["event_ms"] / args.steps
     mlups = cells * args.steps / (fine["event_ms"] * 1e-3) / 1e6
-    step_ms = fine["step_kernel_ms"]  # one launch = two time steps
-    # algorithmic HBM bytes of one launch: the state and the drag coefficient
-    # read once and the state written once, 76 B per cell for two steps
-    achieved = BYTES_PER_LU * cells / (step_ms * 1e-3) / 1e9
+    step_ms = fine["step_kernel_ms"]  # one launch = DEPTH time steps
+    # The multi-step kernel moves the state through HBM once per DEPTH steps;
+    # its bound is the VALU. achieved: the collisions' FP64 arithmetic per
+    # launch (DEPTH x cells lattice updates x FLOPS_PER_LU) over the launch.
+    t_launch = step_ms * 1e-3
+    achieved = FLOPS_PER_LU * DEPTH * cells / t_launch / 1e12
+    hbm_gbs = BYTES_PER_LU * cells / t_launch / 1e9
     traffic = _traffic_per_launch()
+    valu = _valu_per_launch()
     result = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -234,13 +253,19 @@ def main():
                                "corr 32), tau 0.8, g 1e-6, walls in y, FP32 deviation "
                                "populations, mean-velocity reduction every 100 steps",
                    "nx": n, "ny": n, "check_every": 100},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                      "traffic": traffic,
-                     "kernel": "k_step2<float, walls, scalar> (two time steps per launch)",
+                     "kernel": f"k_stepd<float, walls, scalar, {DEPTH}> ({DEPTH} time steps per launch)",
                      "avg_launch_us": round(step_ms * 1e3, 3),
-                     "bytes_per_launch": BYTES_PER_LU * cells,
-                     "lattice_updates_per_launch": 2 * cells},
+                     "flops_per_launch": FLOPS_PER_LU * DEPTH * cells,
+                     "lattice_updates_per_launch": DEPTH * cells,
+                     "hbm_bytes_per_launch_algorithmic": BYTES_PER_LU * cells,
+                     "hbm_achieved_gbs": round(hbm_gbs, 1),
+                     "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                     "valu_issue_frac": None if valu is None else
+                     round(valu / (t_launch * VALU_ISSUE_PER_S), 4),
+                     "single_step_hbm_equivalent_gbs": round(mlups * 1e6 * BYTES_PER_LU / 1e9, 1)},
         "wall_s": round(fine["wall_s"], 3),
     }
     result["step_forms"] = bench_forms(L, torch, kappa)

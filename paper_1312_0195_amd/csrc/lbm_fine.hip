@@ -31,6 +31,7 @@
 #include <cstring>
 #include <algorithm>
 #include <new>
+#include <type_traits>
 
 #include "lbm_internal.h"
 
@@ -204,17 +205,17 @@ __device__ __forceinline__ int xcd_block(int bid, int nb)
 // forms: u from Eq. explicit-u-in-Guo (one division), the drag force f_m of
 // Eq. f_m-depends-on-u, f_eq at u (Eq. feq), the forcing term F_a of Eq.
 // Fi-of-Guo and the update of Eq. f-evolution-of-Guo. coef holds eps nu / kappa.
-template <typename R, bool FF, class M>
-__device__ __forceinline__ void collide_cell_guo(const StepArgs<R> &a, double f[9], int c)
+template <typename R, bool FF, class CM, class FM>
+__device__ __forceinline__ void collide_guo(const StepArgs<R> &a, double f[9], int c, int cf,
+                                            const CM &cm, const FM &fm)
 {
-    const M cm{a.coef, nullptr, a.cstride}, fm{a.hforce, nullptr, a.cstride};
     double dr, jx, jy;
     moments(f, dr, jx, jy);
     const double rho = a.rho0_d + dr;
     double hgx, hgy;  // eps G / 2
     if (FF) {
-        hgx = (double)fm.ld(0, c);
-        hgy = (double)fm.ld(1, c);
+        hgx = (double)fm.ld(0, cf);
+        hgy = (double)fm.ld(1, cf);
     } else {
         hgx = a.hegx_d;
         hgy = a.hegy_d;
@@ -240,23 +241,37 @@ __device__ __forceinline__ void collide_cell_guo(const StepArgs<R> &a, double f[
     f[8] = f[8] + om * (w5 * (dr + ru3x - ru3y) - f[8]) + w5 * kf * (fmx - fmy);
 }
 
+// Coefficient sources besides the plane accessors: one value already in a
+// register, or an array in LDS indexed like the tile buffer.
+template <typename R>
+struct OneCoef {
+    R v;
+    __device__ R ld(int, int) const { return v; }
+};
+template <typename R>
+struct LdsCoef {
+    const R *p;
+    __device__ R ld(int, int i) const { return p[i]; }
+};
+
 // PK: 1 scalar drag coefficient D, 4 tensor M (Shan-Chen form); 0 the Guo
-// form with coef = eps nu / kappa.
-template <typename R, int PK, bool FF, class M = GMem<R>>
-__device__ __forceinline__ void collide_cell(const StepArgs<R> &a, double f[9], int c)
+// form with coef = eps nu / kappa. Coefficients come from cm at index c, the
+// per-cell force from fm at index cf.
+template <typename R, int PK, bool FF, class CM, class FM>
+__device__ __forceinline__ void collide_m(const StepArgs<R> &a, double f[9], int c, int cf, const CM &cm,
+                                          const FM &fm)
 {
     if (PK == 0) {
-        collide_cell_guo<R, FF, M>(a, f, c);
+        collide_guo<R, FF>(a, f, c, cf, cm, fm);
         return;
     }
-    const M cm{a.coef, nullptr, a.cstride}, fm{a.hforce, nullptr, a.cstride};
     double dr, jx, jy;
     moments(f, dr, jx, jy);
     const double rho = a.rho0_d + dr;
     double hx, hy;
     if (FF) {
-        hx = jx + (double)fm.ld(0, c) * rho;
-        hy = jy + (double)fm.ld(1, c) * rho;
+        hx = jx + (double)fm.ld(0, cf) * rho;
+        hy = jy + (double)fm.ld(1, cf) * rho;
     } else {
         hx = jx + a.hegx_d * rho;
         hy = jy + a.hegy_d * rho;
@@ -292,6 +307,15 @@ __device__ __forceinline__ void collide_cell(const StepArgs<R> &a, double f[9], 
     f[8] = omc * f[8] + (cc + qq);
 }
 
+// Collision of lattice cell c with coefficients and force read through plane
+// accessors of type M.
+template <typename R, int PK, bool FF, class M = GMem<R>>
+__device__ __forceinline__ void collide_cell(const StepArgs<R> &a, double f[9], int c)
+{
+    const M cm{a.coef, nullptr, a.cstride}, fm{a.hforce, nullptr, a.cstride};
+    collide_m<R, PK, FF>(a, f, c, c, cm, fm);
+}
+
 // One time step per launch: pull, collide, store (one HBM pass).
 template <typename R, bool WALLS, int PK, bool FF>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
@@ -317,69 +341,159 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
     for (int q = 0; q < 9; ++q) o[q * S + c] = (R)f[q];
 }
 
-// Tile of the two-step kernel: TX x TY output cells per workgroup.
-template <typename R> struct Tile2;
-template <> struct Tile2<float> { static constexpr int TX = 64, TY = 64, BS = 1024; };
-template <> struct Tile2<double> { static constexpr int TX = 32, TY = 16, BS = 256; };
+// Tiles of the multi-step kernel, per storage type and depth D (time steps
+// per launch): TX x TY output cells per workgroup of BS threads. The LDS
+// holds one buffer of 9 x (TX + 2 (D - 1)) x (TY + 2 (D - 1)) values.
+#ifndef LBM_TILE6
+#define LBM_TILE6 64, 16, 512
+#endif
+#ifndef LBM_TILE4
+#define LBM_TILE4 64, 16, 512
+#endif
+template <int X, int Y, int B> struct TileShape { static constexpr int TX = X, TY = Y, BS = B; };
+template <typename R, int D> struct TileD;
+template <> struct TileD<float, 2> : TileShape<64, 64, 1024> {};
+template <> struct TileD<float, 4> : TileShape<LBM_TILE4> {};
+template <> struct TileD<float, 6> : TileShape<LBM_TILE6> {};
+template <> struct TileD<double, 2> : TileShape<32, 16, 256> {};
 
-// Two time steps per launch (temporal blocking). Phase 1 takes step t on the
-// workgroup's tile plus a one-cell halo, pulling from HBM and keeping the
+// D time steps per launch (temporal blocking). Phase 1 takes step t on the
+// workgroup's tile plus a (D - 1)-cell halo, pulling from HBM and keeping the
 // post-collision values in LDS, rounded to the storage type exactly as a
-// store to HBM would round them; phase 2 takes step t + 1 on the tile,
-// pulling from LDS, and writes to HBM. The result is bit-identical to two
-// one-step launches while HBM sees one read and one write of the state per
-// two steps (plus the halo, which neighbouring tiles mostly find in L2).
-template <typename R, bool WALLS, int PK, bool FF>
-__global__ __launch_bounds__(Tile2<R>::BS) void k_step2(StepArgs<R> a)
+// store to HBM would round them; phases 2 .. D - 1 take the next steps on
+// regions that shrink by one cell per step, in place in LDS; phase D takes the
+// last step on the tile and writes to HBM. The result is bit-identical to D
+// one-step launches while HBM sees one read and one write of the state per D
+// steps (plus the halo, which neighbouring tiles mostly find in L2). Loads and
+// stores go through BMem (32-bit offsets, plane bases in scalar registers).
+template <typename R, bool WALLS, int PK, bool FF, int D>
+__global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
 {
-    constexpr int TX = Tile2<R>::TX, TY = Tile2<R>::TY, BS = Tile2<R>::BS;
-    constexpr int HX = TX + 2, HY = TY + 2, HN = HX * HY;
-    __shared__ R h[9][HN];
+    constexpr int TX = TileD<R, D>::TX, TY = TileD<R, D>::TY, BS = TileD<R, D>::BS;
+    constexpr int H = D - 1;
+    constexpr int AX = TX + 2 * H, AY = TY + 2 * H, AN = AX * AY;
+    constexpr int KM = (D > 2) ? ((AX - 2) * (AY - 2) + BS - 1) / BS : 1;  // cells per thread, phase 2
+    // scalar coefficients without a force field are read once from HBM and
+    // kept in LDS next to the populations
+    constexpr bool CL = (PK != 4) && !FF && 10 * AN * sizeof(R) <= 160 * 1024;
+    __shared__ R P[9][AN];
+    __shared__ R Dl[CL ? AN : 1];
     const int nx = a.nx, ny = a.ny;
     const int ntx = (nx + TX - 1) / TX;
     const int bid = xcd_block(blockIdx.x, gridDim.x);
     const int y0 = (bid / ntx) * TY, x0 = (bid % ntx) * TX;
     const int tw = min(TX, nx - x0), th = min(TY, ny - y0);  // ragged tiles at the far edges
     const BMem<R> mem{a.fin, a.fout, a.stride};
-    for (int i = threadIdx.x; i < HN; i += BS) {
-        const int hx = i % HX, hy = i / HX;
-        if (hx > tw + 1 || hy > th + 1) continue;
-        int x = x0 - 1 + hx;
-        x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
-        int y = y0 - 1 + hy;
-        if (WALLS) {
-            if (y < 0 || y >= ny) continue;  // beyond a wall: never pulled
+    // lattice cell of P coordinate (px, py); false beyond a wall
+    // (x0 - H + px lies in [-H, nx + H): one wrap suffices unless the grid
+    // is narrower than the halo)
+    const bool wide = nx > H, tall = ny > H;
+    auto cell_of = [&](int px, int py, int &x, int &y) -> bool {
+        x = x0 - H + px;
+        if (wide) {
+            x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
         } else {
-            y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+            x %= nx;
+            x = x < 0 ? x + nx : x;
         }
+        y = y0 - H + py;
+        if (WALLS) return y >= 0 && y < ny;
+        if (tall) {
+            y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        } else {
+            y %= ny;
+            y = y < 0 ? y + ny : y;
+        }
+        return true;
+    };
+    // the nine pre-collision values of P cell c (lattice row y) from the buffer
+    auto pull_lds = [&](int c, int y, double f[9]) {
+        const bool lo = WALLS && y == 0, hi = WALLS && y == ny - 1;
+        f[0] = (double)P[0][c];
+        f[1] = (double)P[1][c - 1];
+        f[3] = (double)P[3][c + 1];
+        f[2] = (double)(lo ? P[4][c] : P[2][c - AX]);
+        f[5] = (double)(lo ? P[7][c] : P[5][c - AX - 1]);
+        f[6] = (double)(lo ? P[8][c] : P[6][c - AX + 1]);
+        f[4] = (double)(hi ? P[2][c] : P[4][c + AX]);
+        f[7] = (double)(hi ? P[5][c] : P[7][c + AX + 1]);
+        f[8] = (double)(hi ? P[6][c] : P[8][c + AX - 1]);
+    };
+    // phase 1: region [0, tw + 2H) x [0, th + 2H) from HBM
+    const int w1 = tw + 2 * H, h1 = th + 2 * H;
+    for (int i = threadIdx.x; i < AN; i += BS) {
+        const int px = i % AX, py = i / AX;
+        int x, y;
+        if (px >= w1 || py >= h1 || !cell_of(px, py, x, y)) continue;
         R fr[9];
         pullm<R, WALLS>(mem, nx, ny, x, y, fr);
         double f[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) f[q] = (double)fr[q];
-        collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
+        if constexpr (CL) {
+            const R d = BMem<R>{a.coef, nullptr, a.cstride}.ld(0, y * nx + x);
+            Dl[i] = d;
+            collide_m<R, PK, FF>(a, f, 0, 0, OneCoef<R>{d}, OneCoef<R>{d});
+        } else {
+            collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
+        }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) h[q][i] = (R)f[q];
+        for (int q = 0; q < 9; ++q) P[q][i] = (R)f[q];
+    }
+    // phases 2 .. D - 1: region [ph, w1 - ph) x [ph, h1 - ph), in place;
+    // threads walk the full-tile shape (compile-time divisors) and skip the
+    // part a ragged tile lacks
+#pragma unroll
+    for (int ph = 1; ph < H; ++ph) {
+        const int RW = AX - 2 * ph, RN = RW * (AY - 2 * ph);
+        __syncthreads();
+        R pr[KM][9];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = threadIdx.x + k * BS;
+            const int px = ph + i % RW, py = ph + i / RW;
+            int x, y;
+            if (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y)) {
+                double f[9];
+                pull_lds(py * AX + px, y, f);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) pr[k][q] = (R)f[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = threadIdx.x + k * BS;
+            const int px = ph + i % RW, py = ph + i / RW;
+            int x, y;
+            if (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y)) {
+                double f[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) f[q] = (double)pr[k][q];
+                const int c = py * AX + px;
+                if constexpr (CL)
+                    collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
+                else
+                    collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) P[q][c] = (R)f[q];
+            }
+        }
     }
     __syncthreads();
+    // phase D: the tile, from LDS to HBM
     for (int i = threadIdx.x; i < TX * TY; i += BS) {
         const int lx = i % TX, ly = i / TX;
         if (lx >= tw || ly >= th) continue;
         const int x = x0 + lx, y = y0 + ly;
-        const int c = (ly + 1) * HX + (lx + 1);
         double f[9];
-        f[0] = (double)h[0][c];
-        f[1] = (double)h[1][c - 1];
-        f[3] = (double)h[3][c + 1];
-        const bool lo = WALLS && y == 0, hi = WALLS && y == ny - 1;
-        f[2] = (double)(lo ? h[4][c] : h[2][c - HX]);
-        f[5] = (double)(lo ? h[7][c] : h[5][c - HX - 1]);
-        f[6] = (double)(lo ? h[8][c] : h[6][c - HX + 1]);
-        f[4] = (double)(hi ? h[2][c] : h[4][c + HX]);
-        f[7] = (double)(hi ? h[5][c] : h[7][c + HX + 1]);
-        f[8] = (double)(hi ? h[6][c] : h[8][c + HX - 1]);
+        const int c = (ly + H) * AX + (lx + H);
+        pull_lds(c, y, f);
         const int g = y * nx + x;
-        collide_cell<R, PK, FF, BMem<R>>(a, f, g);
+        if constexpr (CL)
+            collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
+        else
+            collide_cell<R, PK, FF, BMem<R>>(a, f, g);
 #pragma unroll
         for (int q = 0; q < 9; ++q) mem.st(q, g, (R)f[q]);
     }
@@ -737,14 +851,34 @@ struct StepFn {
     static void run(const lbm_handle *h) { launch_step_t<R, W, PK, FF>(h); }
 };
 template <typename R, bool W, int PK, bool FF>
-struct Step2Fn {
-    static void run(const lbm_handle *h)
+struct StepDFn {
+    template <int D>
+    static void launch(const lbm_handle *h)
     {
-        constexpr int TX = Tile2<R>::TX, TY = Tile2<R>::TY, BS = Tile2<R>::BS;
+        constexpr int TX = TileD<R, D>::TX, TY = TileD<R, D>::TY, BS = TileD<R, D>::BS;
         const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
-        hipLaunchKernelGGL((k_step2<R, W, PK, FF>), dim3(ntx * nty), dim3(BS), 0, h->stream, step_args<R>(h));
+        hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D>), dim3(ntx * nty), dim3(BS), 0, h->stream,
+                           step_args<R>(h));
+    }
+    static void run(const lbm_handle *h, int depth)
+    {
+        if constexpr (std::is_same<R, float>::value) {
+            if (depth == 6) return launch<6>(h);
+            if (depth == 4) return launch<4>(h);
+        }
+        launch<2>(h);
     }
 };
+
+// Steps per launch: the deepest available depth that fits before the next
+// check (or the end); 1 runs the single-step kernel.
+int launch_depth(const lbm_handle *h, int64_t room)
+{
+    const bool f64 = h->p.pop_dtype == LBM_F64;
+    if (!f64 && room >= 6) return 6;
+    if (!f64 && room >= 4) return 4;
+    return room >= 2 ? 2 : 1;
+}
 template <typename R, bool W, int PK, bool FF>
 struct FieldsFn {
     static void run(const lbm_handle *h, double *u, double *rho, double *part)
@@ -876,11 +1010,11 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t max_steps, double tol, int
     bool last_checked = false;
     double u[2] = {0.0, 0.0};
     while (done < max_steps) {
-        // two steps per launch unless a check or the end falls in between
+        // several steps per launch unless a check or the end falls in between
         const int64_t to_check = check_every > 0 ? check_every - done % check_every : max_steps - done;
-        const int64_t n = std::min<int64_t>(to_check, max_steps - done) >= 2 ? 2 : 1;
-        if (n == 2)
-            dispatch<Step2Fn>(h);
+        const int n = launch_depth(h, std::min<int64_t>(to_check, max_steps - done));
+        if (n >= 2)
+            dispatch<StepDFn>(h, n);
         else
             dispatch<StepFn>(h);
         h->cur ^= 1;

@@ -1,4 +1,4 @@
-"""Learned K_eff surrogate with the batched local LBM as fallback and judge.
+"""Learned K_eff surrogate with the batched local LBM as fallback and as reference.
 
 The network (see include/lbm.h, lbm_cnn_*) maps a periodic 32 x 32 patch of
 log K to (log kxx, log kyy) of the effective permeability that the local

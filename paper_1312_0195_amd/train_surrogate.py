@@ -9,7 +9,7 @@
 3. Test set: 65536 patches, about 90% from the training distribution (fresh
    seeds) and 10% outside it (sigma 3.5 at correlation length 8; sigma 1 at
    correlation length 1.5; 8-row channels of K x 1e3 on a sigma-1 field).
-   Every test patch is also labelled by the LBM, the judge of the network's
+   Every test patch is also labelled by the LBM, the reference for the network's
    error. Reported: K_eff error of in-range patches (p50, p95, max), the same
    for the geometric-mean estimate exp(mean log K), how many patches the
    range detector sends to the LBM, and patches/s of network + fallback vs
@@ -86,7 +86,7 @@ def evaluate(model: S.Surrogate, big, x0, y0, is_oor, sweep_nsym=(1, 2, 4, 8)):
     import torch
     kind = np.asarray(is_oor).astype(np.int8)
     is_oor = kind > 0
-    # LBM labels for every test patch (the judge), timed: the LBM-only path
+    # LBM labels for every test patch (the reference), timed: the LBM-only path
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     y_lbm, flags = S.label_patches(big, x0, y0)

@@ -148,23 +148,50 @@ def test_fine_converges_to_oracle_steady_state(L):
         assert _rel_field_err(u.cpu().numpy(), np.stack([uxo, uyo])) < 10 * tol_u
 
 
-@pytest.mark.parametrize("nx,ny,walls", [(2048, 96, 1), (130, 70, 0), (64, 33, 1), (5, 3, 0)])
+@pytest.mark.parametrize("nx,ny,walls", [(2048, 96, 1), (130, 70, 0), (200, 37, 1), (64, 33, 1),
+                                         (5, 3, 0), (3, 40, 1)])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_two_step_launches_match_single_steps_bitwise(L, nx, ny, walls, dtype):
-    """lbm_step runs two steps per launch (temporal blocking in LDS) whenever
-    no check falls in between; the state must equal that of single-step
-    launches bit for bit (ragged tiles, walls and periodic y included)."""
+def test_multi_step_launches_match_single_steps_bitwise(L, nx, ny, walls, dtype):
+    """lbm_step advances several steps per launch (temporal blocking in LDS:
+    6, 4 or 2 steps with FP32 state, 2 with FP64) whenever no check falls in
+    between; the state must equal that of single-step launches bit for bit
+    (ragged tiles, walls, periodic y, grids smaller than the halo)."""
     dt = L.LBM_F64 if dtype == "f64" else L.LBM_F32_SHIFTED
     k = I.lognormal_kappa(nx, ny, 1.5, 6.0, seed=11)
     p = L.make_params(nx, ny, 0.7, 0.4, 0.1, 1.0, 1e-6, 3e-7, walls, dt)
     a = L.FineSolver(p, k)
     b = L.FineSolver(p, k)
-    a.step(37)                 # 18 two-step launches and one single step
-    for _ in range(37):
+    for n in (37, 11, 3):      # FP32: 6x6 + 1, 6 + 4 + 1, 2 + 1 steps per launch
+        a.step(n)
+    for _ in range(51):
         b.step(1)              # single-step launches only
     fa = a.populations().cpu().numpy()
     fb = b.populations().cpu().numpy()
     assert np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("scheme,perm_kind,force", [(0, 4, True), (1, 1, True), (0, 1, True)])
+def test_multi_step_launches_bitwise_all_kernel_forms(L, scheme, perm_kind, force):
+    """The same on the other kernel forms: tensor permeability, the Guo form,
+    a per-cell force field (periodic y, ragged tiles)."""
+    nx, ny = 150, 45
+    rng = np.random.default_rng(4)
+    if perm_kind == 4:
+        kxx = np.exp(rng.standard_normal((ny, nx)))
+        kyy = np.exp(rng.standard_normal((ny, nx)))
+        kxy = 0.2 * np.sqrt(kxx * kyy) * rng.uniform(-1, 1, (ny, nx))
+        k = np.stack([kxx, kxy, 0.5 * kxy, kyy], axis=-1)
+    else:
+        k = I.lognormal_kappa(nx, ny, 1.5, 6.0, seed=12)
+    f = 1e-6 * rng.standard_normal((ny, nx, 2)) if force else None
+    p = L.make_params(nx, ny, 0.9, 0.4, 0.1, 1.0, 1e-6, 0.0, 0, L.LBM_F32_SHIFTED, perm_kind, scheme)
+    a = L.FineSolver(p, k, f)
+    b = L.FineSolver(p, k, f)
+    a.step(24)                 # 6 x 4 steps per launch
+    a.step(5)                  # 4 + 1
+    for _ in range(29):
+        b.step(1)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
 
 
 def test_set_populations_resumes_oracle_state(L):
