@@ -344,8 +344,11 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
 // Tiles of the multi-step kernel, per storage type and depth D (time steps
 // per launch): TX x TY output cells per workgroup of BS threads. The LDS
 // holds one buffer of 9 x (TX + 2 (D - 1)) x (TY + 2 (D - 1)) values.
+#ifndef LBM_DEEP
+#define LBM_DEEP 6  // steps per launch of the deepest kernel (FP32 state)
+#endif
 #ifndef LBM_TILE6
-#define LBM_TILE6 64, 16, 512
+#define LBM_TILE6 48, 24, 512
 #endif
 #ifndef LBM_TILE4
 #define LBM_TILE4 64, 16, 512
@@ -354,7 +357,9 @@ template <int X, int Y, int B> struct TileShape { static constexpr int TX = X, T
 template <typename R, int D> struct TileD;
 template <> struct TileD<float, 2> : TileShape<64, 64, 1024> {};
 template <> struct TileD<float, 4> : TileShape<LBM_TILE4> {};
-template <> struct TileD<float, 6> : TileShape<LBM_TILE6> {};
+template <> struct TileD<float, LBM_DEEP> : TileShape<LBM_TILE6> {};
+constexpr int kDeep = LBM_DEEP;
+static_assert(kDeep > 4, "the deepest kernel must take more than 4 steps");
 template <> struct TileD<double, 2> : TileShape<32, 16, 256> {};
 
 // D time steps per launch (temporal blocking). Phase 1 takes step t on the
@@ -384,6 +389,11 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
     const int y0 = (bid / ntx) * TY, x0 = (bid % ntx) * TX;
     const int tw = min(TX, nx - x0), th = min(TY, ny - y0);  // ragged tiles at the far edges
     const BMem<R> mem{a.fin, a.fout, a.stride};
+    // Interior tiles (most of a large grid): every cell the launch touches,
+    // including the neighbours phase 1 pulls from, lies inside the grid away
+    // from the walls, so no wrap, wall or ragged-edge test is needed.
+    const bool interior = tw == TX && th == TY && x0 >= H + 1 && x0 + TX + H <= nx - 1 &&
+                          y0 >= H + 1 && y0 + TY + H <= ny - 1;
     // lattice cell of P coordinate (px, py); false beyond a wall
     // (x0 - H + px lies in [-H, nx + H): one wrap suffices unless the grid
     // is narrower than the halo)
@@ -407,8 +417,8 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
         return true;
     };
     // the nine pre-collision values of P cell c (lattice row y) from the buffer
-    auto pull_lds = [&](int c, int y, double f[9]) {
-        const bool lo = WALLS && y == 0, hi = WALLS && y == ny - 1;
+    auto pull_lds = [&](int c, int y, bool edge, double f[9]) {
+        const bool lo = WALLS && edge && y == 0, hi = WALLS && edge && y == ny - 1;
         f[0] = (double)P[0][c];
         f[1] = (double)P[1][c - 1];
         f[3] = (double)P[3][c + 1];
@@ -419,84 +429,110 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
         f[7] = (double)(hi ? P[5][c] : P[7][c + AX + 1]);
         f[8] = (double)(hi ? P[6][c] : P[8][c + AX - 1]);
     };
-    // phase 1: region [0, tw + 2H) x [0, th + 2H) from HBM
     const int w1 = tw + 2 * H, h1 = th + 2 * H;
-    for (int i = threadIdx.x; i < AN; i += BS) {
-        const int px = i % AX, py = i / AX;
-        int x, y;
-        if (px >= w1 || py >= h1 || !cell_of(px, py, x, y)) continue;
-        R fr[9];
-        pullm<R, WALLS>(mem, nx, ny, x, y, fr);
-        double f[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = (double)fr[q];
-        if constexpr (CL) {
-            const R d = BMem<R>{a.coef, nullptr, a.cstride}.ld(0, y * nx + x);
-            Dl[i] = d;
-            collide_m<R, PK, FF>(a, f, 0, 0, OneCoef<R>{d}, OneCoef<R>{d});
-        } else {
-            collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
-        }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) P[q][i] = (R)f[q];
-    }
-    // phases 2 .. D - 1: region [ph, w1 - ph) x [ph, h1 - ph), in place;
-    // threads walk the full-tile shape (compile-time divisors) and skip the
-    // part a ragged tile lacks
-#pragma unroll
-    for (int ph = 1; ph < H; ++ph) {
-        const int RW = AX - 2 * ph, RN = RW * (AY - 2 * ph);
-        __syncthreads();
-        R pr[KM][9];
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = threadIdx.x + k * BS;
-            const int px = ph + i % RW, py = ph + i / RW;
+    auto body = [&](auto fast_tag) {
+        constexpr bool FAST = decltype(fast_tag)::value;
+        // phase 1: region [0, tw + 2H) x [0, th + 2H) from HBM
+        for (int i = threadIdx.x; i < AN; i += BS) {
+            const int px = i % AX, py = i / AX;
             int x, y;
-            if (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y)) {
-                double f[9];
-                pull_lds(py * AX + px, y, f);
+            R fr[9];
+            if constexpr (FAST) {
+                x = x0 - H + px;
+                y = y0 - H + py;
+                const int c = y * nx + x;
+                fr[0] = mem.ld(0, c);
+                fr[1] = mem.ld(1, c - 1);
+                fr[3] = mem.ld(3, c + 1);
+                fr[2] = mem.ld(2, c - nx);
+                fr[5] = mem.ld(5, c - nx - 1);
+                fr[6] = mem.ld(6, c - nx + 1);
+                fr[4] = mem.ld(4, c + nx);
+                fr[7] = mem.ld(7, c + nx + 1);
+                fr[8] = mem.ld(8, c + nx - 1);
+            } else {
+                if (px >= w1 || py >= h1 || !cell_of(px, py, x, y)) continue;
+                pullm<R, WALLS>(mem, nx, ny, x, y, fr);
+            }
+            double f[9];
 #pragma unroll
-                for (int q = 0; q < 9; ++q) pr[k][q] = (R)f[q];
+            for (int q = 0; q < 9; ++q) f[q] = (double)fr[q];
+            if constexpr (CL) {
+                const R d = BMem<R>{a.coef, nullptr, a.cstride}.ld(0, y * nx + x);
+                Dl[i] = d;
+                collide_m<R, PK, FF>(a, f, 0, 0, OneCoef<R>{d}, OneCoef<R>{d});
+            } else {
+                collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) P[q][i] = (R)f[q];
+        }
+        // phases 2 .. D - 1: region [ph, w1 - ph) x [ph, h1 - ph), in place;
+        // threads walk the full-tile shape (compile-time divisors) and skip
+        // the part a ragged tile lacks
+#pragma unroll
+        for (int ph = 1; ph < H; ++ph) {
+            const int RW = AX - 2 * ph, RN = RW * (AY - 2 * ph);
+            __syncthreads();
+            R pr[KM][9];
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const int i = threadIdx.x + k * BS;
+                const int px = ph + i % RW, py = ph + i / RW;
+                int x = x0 - H + px, y = y0 - H + py;
+                const bool in = FAST ? i < RN
+                                     : (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y));
+                if (in) {
+                    double f[9];
+                    pull_lds(py * AX + px, y, !FAST, f);
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) pr[k][q] = (R)f[q];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const int i = threadIdx.x + k * BS;
+                const int px = ph + i % RW, py = ph + i / RW;
+                int x = x0 - H + px, y = y0 - H + py;
+                const bool in = FAST ? i < RN
+                                     : (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y));
+                if (in) {
+                    double f[9];
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) f[q] = (double)pr[k][q];
+                    const int c = py * AX + px;
+                    if constexpr (CL)
+                        collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
+                    else
+                        collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) P[q][c] = (R)f[q];
+                }
             }
         }
         __syncthreads();
+        // phase D: the tile, from LDS to HBM
+        for (int i = threadIdx.x; i < TX * TY; i += BS) {
+            const int lx = i % TX, ly = i / TX;
+            if (!FAST && (lx >= tw || ly >= th)) continue;
+            const int x = x0 + lx, y = y0 + ly;
+            double f[9];
+            const int c = (ly + H) * AX + (lx + H);
+            pull_lds(c, y, !FAST, f);
+            const int g = y * nx + x;
+            if constexpr (CL)
+                collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
+            else
+                collide_cell<R, PK, FF, BMem<R>>(a, f, g);
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = threadIdx.x + k * BS;
-            const int px = ph + i % RW, py = ph + i / RW;
-            int x, y;
-            if (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y)) {
-                double f[9];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) f[q] = (double)pr[k][q];
-                const int c = py * AX + px;
-                if constexpr (CL)
-                    collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
-                else
-                    collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) P[q][c] = (R)f[q];
-            }
+            for (int q = 0; q < 9; ++q) mem.st(q, g, (R)f[q]);
         }
-    }
-    __syncthreads();
-    // phase D: the tile, from LDS to HBM
-    for (int i = threadIdx.x; i < TX * TY; i += BS) {
-        const int lx = i % TX, ly = i / TX;
-        if (lx >= tw || ly >= th) continue;
-        const int x = x0 + lx, y = y0 + ly;
-        double f[9];
-        const int c = (ly + H) * AX + (lx + H);
-        pull_lds(c, y, f);
-        const int g = y * nx + x;
-        if constexpr (CL)
-            collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
-        else
-            collide_cell<R, PK, FF, BMem<R>>(a, f, g);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) mem.st(q, g, (R)f[q]);
-    }
+    };
+    if (interior)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
 }
 
 // Flow velocity (Eq. u-of-S-C) and density of the current state in FP64, and
@@ -863,7 +899,7 @@ struct StepDFn {
     static void run(const lbm_handle *h, int depth)
     {
         if constexpr (std::is_same<R, float>::value) {
-            if (depth == 6) return launch<6>(h);
+            if (depth == kDeep) return launch<kDeep>(h);
             if (depth == 4) return launch<4>(h);
         }
         launch<2>(h);
@@ -875,7 +911,7 @@ struct StepDFn {
 int launch_depth(const lbm_handle *h, int64_t room)
 {
     const bool f64 = h->p.pop_dtype == LBM_F64;
-    if (!f64 && room >= 6) return 6;
+    if (!f64 && room >= kDeep) return kDeep;
     if (!f64 && room >= 4) return 4;
     return room >= 2 ? 2 : 1;
 }
