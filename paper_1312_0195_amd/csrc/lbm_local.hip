@@ -130,8 +130,11 @@ __device__ __forceinline__ void collide(P f[9], P D, P hegx, P hegy, const Const
     f[8] = omc * f[8] + (cc + qq);
 }
 
-template <int T, typename P>
-__global__ __launch_bounds__(T) void k_local(LocalArgs a)
+// CPT: the most cells any thread of this launch owns (1, 2 or 4); the
+// register arrays are sized by it, so launches of small patches keep fewer
+// registers live and fit more workgroups per CU.
+template <int T, typename P, int CPT>
+__global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_local(LocalArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     P *lds = reinterpret_cast<P *>(lds_raw);
@@ -152,8 +155,8 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
     P hegx = 0, hegy = 0;
     double hegx_d = 0.0, hegy_d = 0.0;
     // per-cell registers
-    P f0[kCPT], Dc[kCPT];
-    int xy[kCPT];
+    P f0[CPT], Dc[CPT];
+    int xy[CPT];
 
     bool need_item = true;
     __syncthreads();
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
                 steps = 0;
                 have_prev = false;
 #pragma unroll
-                for (int k = 0; k < kCPT; ++k) {
+                for (int k = 0; k < CPT; ++k) {
                     const int c = lt + k * G;
                     if (k < C && c < S2) {
                         const int x = c % S, y = c / S;
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
             if (active) {
                 const bool odd = ((steps + st) & 1) != 0;
 #pragma unroll
-                for (int k = 0; k < kCPT; ++k) {
+                for (int k = 0; k < CPT; ++k) {
                     const int c = lt + k * G;
                     if (k < C && c < S2) {
                         const int x = xy[k] & 255, y = xy[k] >> 8;
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(T) void k_local(LocalArgs a)
         double sx = 0.0, sy = 0.0;
         if (active) {
 #pragma unroll
-            for (int k = 0; k < kCPT; ++k) {
+            for (int k = 0; k < CPT; ++k) {
                 const int c = lt + k * G;
                 if (k < C && c < S2) {
                     // even order: A[a - 1][c] holds f_a(x) before collision
@@ -389,19 +392,27 @@ int pow2_at_least(int v)
     return p;
 }
 
-template <int T, typename P>
-lbm_status launch_local(const LocalArgs &a, size_t lds_bytes, int grid, hipStream_t stream)
+template <int T, typename P, int CPT>
+lbm_status launch_local_c(const LocalArgs &a, size_t lds_bytes, int grid, hipStream_t stream)
 {
     if (lds_bytes > 64 * 1024)
-        LBM_HIP(hipFuncSetAttribute((const void *)k_local<T, P>,
+        LBM_HIP(hipFuncSetAttribute((const void *)k_local<T, P, CPT>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     int occ = 0;
-    LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_local<T, P>, T, lds_bytes));
+    LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_local<T, P, CPT>, T, lds_bytes));
     if (occ < 1) return set_error(LBM_EINVAL, "lbm_local_keff: tile does not fit on a CU");
     const int blocks = std::min(grid, device_cu_count() * occ);
-    hipLaunchKernelGGL((k_local<T, P>), dim3(blocks), dim3(T), lds_bytes, stream, a);
+    hipLaunchKernelGGL((k_local<T, P, CPT>), dim3(blocks), dim3(T), lds_bytes, stream, a);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
+}
+
+template <int T, typename P>
+lbm_status launch_local(const LocalArgs &a, size_t lds_bytes, int grid, int cpt, hipStream_t stream)
+{
+    if (cpt <= 1) return launch_local_c<T, P, 1>(a, lds_bytes, grid, stream);
+    if (cpt <= 2) return launch_local_c<T, P, 2>(a, lds_bytes, grid, stream);
+    return launch_local_c<T, P, kCPT>(a, lds_bytes, grid, stream);
 }
 
 }  // namespace
@@ -470,7 +481,6 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     const int T = f64 ? std::min(block_threads, 512) : block_threads;
     const size_t cb = f64 ? 64 : 32;  // LDS bytes per cell (populations 1..8)
     const int budget = lds_budget_bytes() - 2048;
-    size_t lds_max = 0;
     for (int i : order) {
         const int s = h_side[i];
         if (classes.empty() || classes.back().side != s) {
@@ -499,7 +509,6 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
             if (cb * cells > (size_t)budget)
                 return set_error(LBM_EINVAL, std::string(fn) + "patch of side " + std::to_string(s) +
                                                      " does not fit in LDS");
-            lds_max = std::max(lds_max, (size_t)c.nslots * cb * cells);
             classes.push_back(c);
         }
         for (int d = 0; d < 2; ++d)
@@ -557,17 +566,26 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     a.check_every = lp->check_every;
     const int64_t ms = (lp->max_steps + lp->check_every - 1) / lp->check_every * lp->check_every;
     a.max_steps = (int)std::min<int64_t>(ms, (int64_t)1 << 30);
-    // one workgroup per concurrent slot-set: no more than the items need
-    int need = 0;
-    for (const ClassDesc &c : classes) need = std::max(need, (c.count + c.nslots - 1) / c.nslots);
+    // One persistent launch for all classes (largest side first, so small
+    // items fill the tail of large ones), compiled for the most cells any
+    // thread owns (1, 2 or 4): a launch of small patches only keeps fewer
+    // registers live and fits more workgroups per CU. (Splitting a mixed
+    // launch by register shape loses the shared tail and was slower.)
+    // Within a launch, one workgroup per concurrent slot-set, no more than
+    // the items need.
+    int cmax = 1, need = 0;
+    size_t lds = 0;
+    for (const ClassDesc &c : classes) {
+        cmax = std::max(cmax, c.cells_per_thread);
+        need = std::max(need, (c.count + c.nslots - 1) / c.nslots);
+        lds = std::max(lds, (size_t)c.nslots * cb * c.side * c.side);
+    }
+    const int cpt = cmax <= 1 ? 1 : (cmax <= 2 ? 2 : 4);
     const int grid = std::max(1, need);
-    if (f64) {
-        if (T == 256) return launch_local<256, double>(a, lds_max, grid, stream);
-        return launch_local<512, double>(a, lds_max, grid, stream);
-    }
-    switch (T) {
-    case 256: return launch_local<256, float>(a, lds_max, grid, stream);
-    case 512: return launch_local<512, float>(a, lds_max, grid, stream);
-    default: return launch_local<1024, float>(a, lds_max, grid, stream);
-    }
+    if (f64)
+        return (T == 256) ? launch_local<256, double>(a, lds, grid, cpt, stream)
+                          : launch_local<512, double>(a, lds, grid, cpt, stream);
+    if (T == 256) return launch_local<256, float>(a, lds, grid, cpt, stream);
+    if (T == 512) return launch_local<512, float>(a, lds, grid, cpt, stream);
+    return launch_local<1024, float>(a, lds, grid, cpt, stream);
 }

@@ -49,7 +49,7 @@ def test_workspace_bytes_host_only():
 
 @pytest.mark.parametrize("field,value", [("tau", 0.4), ("eps", 0.0), ("eps", 1.5), ("nu", 0.0),
                                          ("nx", 0), ("rho0", -1.0), ("walls_y", 2),
-                                         ("pop_dtype", 7), ("perm_kind", 2)])
+                                         ("pop_dtype", 7), ("perm_kind", 2), ("scheme", 2)])
 def test_init_rejects_invalid_parameters_on_host(field, value):
     p = L.make_params(16, 16, 0.8, 0.4, 0.1, 1.0, 1e-6, 0.0, 1)
     setattr(p, field, value)
@@ -71,3 +71,37 @@ def test_init_rejects_small_workspace_on_host():
 def test_step_rejects_null_handle():
     st = L.lib().lbm_step(None, 10, 0.0, 0, None, None)
     assert st == L.LBM_EINVAL
+
+
+def test_guo_form_requires_scalar_permeability():
+    p = L.make_params(16, 16, 0.8, 0.4, 0.1, 1.0, 1e-6, 0.0, 1, L.LBM_F32_SHIFTED,
+                      L.LBM_PERM_TENSOR, L.LBM_SCHEME_GUO)
+    assert L.lbm_workspace_bytes(p) == 0
+    p.perm_kind = L.LBM_PERM_SCALAR
+    assert L.lbm_workspace_bytes(p) > 0
+
+
+def test_local_rejects_unknown_pop_dtype_on_host():
+    lp = L.lbm_local_params(0.8, 0.4, 0.1, 1e-6, 1e-6, 100, 1000, 5)
+    one = (ctypes.c_int32 * 1)(0)
+    side = (ctypes.c_int32 * 1)(8)
+    mask = (ctypes.c_int32 * 1)(3)
+    fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: validation fails first
+    st = L.lib().lbm_local_keff(ctypes.byref(lp), 1, one, one, side, mask, fake, 8, 8, fake,
+                                None, None, None, 0, 0, fake, 1 << 20, None)
+    assert st == L.LBM_EINVAL
+
+
+def test_cnn_forward_rejects_bad_n_sym_on_host():
+    fake = ctypes.c_void_p(256 * 1024)
+    for n_sym in (0, 9):
+        st = L.lib().lbm_cnn_forward(fake, 4, fake, n_sym, fake, None, fake, 1 << 30, None)
+        assert st == L.LBM_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
