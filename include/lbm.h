@@ -267,6 +267,12 @@ int32_t lbm_cnn_param_count(void);
  * gradient buffers (about 256 KB per patch). */
 size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training);
 
+/* The per-patch statistics of lbm_cnn_forward's d_stats alone (same
+ * arithmetic, bit-identical values), without running the network: lets a
+ * caller decide which patches go to the LBM before, or while, the network
+ * runs. d_logk FP32 [batch][32][32], d_stats FP32 [batch][8]. Asynchronous. */
+lbm_status lbm_patch_stats(int32_t batch, const float *d_logk, float *d_stats, hipStream_t stream);
+
 /* d_pred : FP32 [batch][2] predicted (log kxx, log kyy) of each patch, the
  *          mean over symmetry codes 0..n_sym-1 (1 <= n_sym <= 8, else
  *          LBM_EINVAL) of the network applied to the transformed patch, each

@@ -31,7 +31,7 @@ EXPORTS = (
     "lbm_coarse_workspace_bytes", "lbm_coarse_solve", "lbm_block_average", "lbm_status_str",
     "lbm_last_error",
     "lbm_cnn_param_count", "lbm_cnn_workspace_bytes", "lbm_cnn_forward", "lbm_cnn_gradients",
-    "lbm_cnn_train_step",
+    "lbm_cnn_train_step", "lbm_patch_stats",
 )
 
 
@@ -120,6 +120,8 @@ def lib():
     L.lbm_cnn_param_count.restype = ctypes.c_int32
     L.lbm_cnn_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
     L.lbm_cnn_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_patch_stats.argtypes = [ctypes.c_int32, _vp, _vp, _vp]
+    L.lbm_patch_stats.restype = ctypes.c_int
     L.lbm_cnn_forward.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]
     L.lbm_cnn_forward.restype = ctypes.c_int
@@ -279,6 +281,11 @@ def lbm_cnn_param_count() -> int:
 
 def lbm_cnn_workspace_bytes(batch: int, training: bool) -> int:
     return int(lib().lbm_cnn_workspace_bytes(int(batch), int(bool(training))))
+
+
+def lbm_patch_stats(batch, d_logk, d_stats, stream=None) -> None:
+    _raise(lib().lbm_patch_stats(int(batch), _ptr(d_logk), _ptr(d_stats), _stream(stream)),
+           "lbm_patch_stats")
 
 
 def lbm_cnn_forward(d_params, batch, d_logk, n_sym, d_pred, d_stats, d_ws, ws_bytes,

@@ -70,10 +70,11 @@ def mosaic(fields):
     return big, np.concatenate(x0).astype(np.int32), np.concatenate(y0).astype(np.int32)
 
 
-def label_patches(kappa_big, x0, y0, tol=1e-7, chunk=65536, device="cuda"):
-    """log kxx and log kyy of every 32 x 32 window from the batched LBM."""
+def label_patches(kappa_big, x0, y0, tol=1e-7, chunk=65536, device="cuda", kappa_dev=None):
+    """log kxx and log kyy of every 32 x 32 window from the batched LBM (the
+    field given on the host, or already on the device as kappa_dev)."""
     import torch
-    kd = torch.as_tensor(kappa_big).to(device)
+    kd = kappa_dev if kappa_dev is not None else torch.as_tensor(kappa_big).to(device)
     out = np.empty((len(x0), 2))
     flags = np.empty((len(x0), 2), np.int32)
     for s in range(0, len(x0), chunk):
@@ -234,22 +235,35 @@ class Surrogate:
                    list(d["history"]), int(d["n_sym"]) if "n_sym" in d else 8)
 
 
-def keff_with_fallback(model: Surrogate, kappa_big, x0, y0, device="cuda"):
-    """log kxx, log kyy of the 32 x 32 windows at (x0, y0): the network where a
-    patch is in range, the batched LBM (one launch) where it is not.
-    Returns (log_keff [n, 2], used_lbm [n] bool, timings dict)."""
+def keff_with_fallback(model: Surrogate, kappa_dev, x0, y0, logk_dev, n_sym=None):
+    """log kxx, log kyy of the 32 x 32 windows at (x0, y0) of the device field
+    kappa_dev, whose log patches are logk_dev (FP32 [n, 32, 32], device):
+    the network where a patch is in range, the batched LBM where it is not.
+    The patch statistics come first (lbm_patch_stats); the network then runs
+    on a second stream while the LBM solves the flagged patches.
+    Returns (log_keff [n, 2], used_lbm [n] bool, seconds)."""
     import torch
+    n = len(x0)
+    n_sym = model.n_sym if n_sym is None else n_sym
+    dev = logk_dev.device
+    prm = torch.as_tensor(model.params).to(dev)
+    pred = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    st = torch.empty((n, 8), dtype=torch.float32, device=dev)
+    nb = L.lbm_cnn_workspace_bytes(n, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    side = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    logk = np.stack([np.log(I.cut_patch(kappa_big, a, b, SIDE)) for a, b in zip(x0, y0)])
-    t1 = time.perf_counter()
-    pred, stats = model.predict(logk, device=device)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ok = model.in_range(stats)
-    out = pred.copy()
+    L.lbm_patch_stats(n, logk_dev, st)
+    ok = model.in_range(st.cpu().numpy().astype(np.float64))
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        L.lbm_cnn_forward(prm, n, logk_dev, n_sym, pred, None, ws, nb)
+    y = None
     if (~ok).any():
-        y, _ = label_patches(kappa_big, x0[~ok], y0[~ok])
+        y, _ = label_patches(None, x0[~ok], y0[~ok], kappa_dev=kappa_dev)
+    torch.cuda.synchronize(dev)
+    out = pred.cpu().numpy().astype(np.float64)
+    if y is not None:
         out[~ok] = y
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    return out, ~ok, dict(cut_s=t1 - t0, network_s=t2 - t1, fallback_s=t3 - t2)
+    return out, ~ok, time.perf_counter() - t0

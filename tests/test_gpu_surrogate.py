@@ -213,3 +213,66 @@ def test_adam_step_matches_oracle(L):
     ref = {"w": before.copy()}
     C.adam_step(ref, {"w": g}, {}, lr=1e-3)
     assert np.allclose(prm.cpu().numpy(), ref["w"], rtol=0, atol=2e-6)
+
+
+def test_forward_full_batch_sampled(L):
+    """The benchmark's batch: 65536 patches in one launch with n_sym = 2 and
+    the statistics; 12 sampled patches (first, last, spread) against the
+    oracle's symmetric prediction and statistics."""
+    from paper_1312_0195_amd import surrogate as S
+    from paper_1312_0195_amd import train_surrogate as T
+    model = S.Surrogate.load(T.DEFAULT_MODEL)
+    fields = [f for _, _, f in I.surrogate_fields(1024, 77)]
+    big, x0, y0 = S.mosaic(fields)
+    n = len(x0)
+    assert n == 65536
+    logk = np.stack([np.log(I.cut_patch(big, a, b, 32)) for a, b in zip(x0, y0)]).astype(np.float32)
+    pred, stats = model.predict(logk, n_sym=2)
+    pd = _unflat(model.params, _params(0))
+    idx = np.concatenate([[0, n - 1], np.random.default_rng(5).choice(n, 10, replace=False)])
+    po = C.predict_symmetric(pd, logk[idx].astype(np.float64), 2)
+    err = np.abs(pred[idx] - po)
+    assert err.max() < 2e-2 * (1 + np.abs(po).max()), err.max()
+    xc = logk[idx] - logk[idx].mean(axis=(1, 2), keepdims=True)
+    assert np.allclose(stats[idx, 0], logk[idx].mean(axis=(1, 2)), rtol=1e-5, atol=1e-5)
+    assert np.allclose(stats[idx, 4:], C.series_parallel(xc.astype(np.float64)), atol=2e-5)
+
+
+def test_patch_stats_equal_forward_stats(L):
+    """lbm_patch_stats gives the forward kernel's statistics bit for bit."""
+    p = _params(21)
+    x = _patches(300, 22).astype(np.float32)
+    prm = torch.tensor(_flat(p), device="cuda")
+    xd = torch.tensor(x, device="cuda")
+    pred = torch.empty((300, 2), dtype=torch.float32, device="cuda")
+    st_f = torch.empty((300, 8), dtype=torch.float32, device="cuda")
+    st_s = torch.full((300, 8), float("nan"), dtype=torch.float32, device="cuda")
+    nb = L.lbm_cnn_workspace_bytes(300, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_forward(prm, 300, xd, 2, pred, st_f, ws, nb)
+    L.lbm_patch_stats(300, xd, st_s)
+    torch.cuda.synchronize()
+    assert torch.equal(st_f, st_s)
+    with pytest.raises(L.LbmError):
+        L.lbm_patch_stats(0, xd, st_s)
+
+
+def test_pipelined_fallback_matches_separate_paths(L):
+    """keff_with_fallback (statistics, then the network on a second stream
+    concurrent with the LBM on the flagged patches) returns the network's
+    prediction where in range and the LBM's elsewhere."""
+    from paper_1312_0195_amd import surrogate as S
+    from paper_1312_0195_amd import train_surrogate as T
+    model = S.Surrogate.load(T.DEFAULT_MODEL)
+    big, x0, y0, kind = T.test_set(64 * 12, 0.25, seed=8)
+    kd = torch.as_tensor(big).cuda()
+    logk = np.stack([np.log(I.cut_patch(big, a, b, 32)) for a, b in zip(x0, y0)]).astype(np.float32)
+    xd = torch.as_tensor(logk).cuda()
+    out, used, secs = S.keff_with_fallback(model, kd, x0, y0, xd)
+    pred, stats = model.predict(logk)
+    ok = model.in_range(stats)
+    assert (used == ~ok).all() and used.any() and (~used).any()
+    assert np.array_equal(out[ok], pred[ok])
+    y_lbm, _ = S.label_patches(None, x0[~ok], y0[~ok], kappa_dev=kd)
+    assert np.allclose(out[~ok], y_lbm, rtol=0, atol=1e-12)
+    assert secs > 0

@@ -116,3 +116,24 @@ def test_two_grid_local_keff_reproduces_sec43_values(L):
         patch = S["kappa"][J * 10:(J + 1) * 10, Ii * 10:(Ii + 1) * 10]
         ko = DS.keff_direct(patch, S["tau"] if tau_local is None else tau_local, T.EPS, S["nu"], 1e-6)
         assert np.max(np.abs(keff[J, Ii] - ko)) / abs(ko[0]) < 1e-5
+
+
+def test_upscale_full_size_locals_and_coarse(L):
+    """The upscaling workload at full size (4096 x 4096, sigma 2, correlation
+    length 64, r = 64): the 4096 local problems of 64 x 64 in one launch with
+    sampled K_eff against the oracle's exact fixed point, then the 64 x 64
+    coarse solves (tensor and scalar) to convergence."""
+    from paper_1312_0195_amd import upscale as U
+    w = I.workload_upscale(seed=1)
+    kd = torch.as_tensor(w["kappa"]).cuda()
+    keff, ok = U.local_tensor(kd, 64, TAU, EPS, NU, G)
+    assert ok and keff.shape == (64, 64, 4)
+    for J, Ii in [(0, 0), (63, 63), (17, 40)]:
+        patch = w["kappa"][J * 64:(J + 1) * 64, Ii * 64:(Ii + 1) * 64]
+        ko = DS.keff_direct(patch, TAU, EPS, NU, G)
+        scale = max(abs(ko[0]), abs(ko[3]))
+        assert np.max(np.abs(keff[J, Ii] - ko)) / scale < 1e-4
+    for mode in (L.LBM_KEFF_TENSOR, L.LBM_KEFF_SCALAR):
+        u, steps, st = U.coarse_solve(w["kappa"].shape, keff, 64, TAU, EPS, NU, G, mode, 1e-6)
+        assert st == L.LBM_OK and np.isfinite(u).all()
+        assert 0 < np.mean(u[0])  # flow follows the drive
