@@ -333,6 +333,43 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     }
 }
 
+// Statistics of each patch only (the range detector's inputs), computed
+// exactly as k_forward computes them for its d_stats output.
+__global__ __launch_bounds__(kT) void k_stats(const float *__restrict__ logk, int batch,
+                                              float *__restrict__ stats)
+{
+    __shared__ float xs[kPix];
+    __shared__ float red[kWaves];
+    __shared__ float tmp[128];
+    __shared__ float feat[4];
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+        const float *lk = logk + (size_t)b * kPix;
+        const float v0 = lk[tid], v1 = lk[tid + kT];
+        const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
+        const float x0 = v0 - m, x1 = v1 - m;
+        xs[tid] = x0;
+        xs[tid + kT] = x1;
+        __syncthreads();
+        const int p0 = tid, p1 = tid + kT;
+        const float rx = x0 * xs[(p0 & ~31) | wrap32(p0 + 1)] + x1 * xs[(p1 & ~31) | wrap32(p1 + 1)];
+        const float ry = x0 * xs[(p0 + kSide) & (kPix - 1)] + x1 * xs[(p1 + kSide) & (kPix - 1)];
+        const float var = block_sum_fixed(x0 * x0 + x1 * x1, red) * (1.0f / kPix);
+        const float cx = block_sum_fixed(rx, red) * (1.0f / kPix);
+        const float cy = block_sum_fixed(ry, red) * (1.0f / kPix);
+        series_parallel(xs, tmp, feat);
+        if (tid == 0) {
+            float *st = stats + 8 * (size_t)b;
+            st[0] = m;
+            st[1] = sqrtf(var);
+            st[2] = var > 0.f ? cx / var : 0.f;
+            st[3] = var > 0.f ? cy / var : 0.f;
+        }
+        if (tid < 4) stats[8 * (size_t)b + 4 + tid] = feat[tid];
+        __syncthreads();
+    }
+}
+
 // Head backward per patch (one wave per patch), FP32. Loss L = mean over the
 // batch and both outputs of (prediction - target)^2. Writes the patch's head
 // gradient, dL/dpool and its loss term.
@@ -713,6 +750,16 @@ lbm_status gradients(const float *prm, int batch, const float *logk, const int8_
 using namespace lbm;
 
 extern "C" int32_t lbm_cnn_param_count(void) { return kNParams; }
+
+extern "C" lbm_status lbm_patch_stats(int32_t batch, const float *d_logk, float *d_stats, hipStream_t stream)
+{
+    if (batch < 1 || !d_logk || !d_stats)
+        return set_error(LBM_EINVAL, "lbm_patch_stats: batch < 1 or NULL argument");
+    const int grid = std::min(batch, 8 * device_cu_count());
+    hipLaunchKernelGGL(k_stats, dim3(grid), dim3(kT), 0, stream, d_logk, batch, d_stats);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
 
 extern "C" size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training)
 {
