@@ -106,17 +106,30 @@ def steady_state(p: O.Params, perm, g=(0.0, 0.0), force=None) -> np.ndarray:
     return (f_rest + d).reshape(p.ny, p.nx, 9)
 
 
-def steady_mean_velocity(p: O.Params, perm, g=(0.0, 0.0), force=None) -> np.ndarray:
+def steady_mean_velocity(p: O.Params, perm, g=(0.0, 0.0), force=None,
+                         margin: int = 0) -> np.ndarray:
+    """Mean flow velocity of the steady state over the whole domain or, with
+    margin m > 0, over the inner window [m, nx - m) x [m, ny - m) only
+    (oversampling: the cells next to the artificial periodic boundary are
+    left out of the average)."""
     f = steady_state(p, perm, g, force)
-    return O.mean_velocity(p, perm, f, g, force)
+    if margin == 0:
+        return O.mean_velocity(p, perm, f, g, force)
+    _, ux, uy = O.moments(p, perm, f, g, force)
+    w = (slice(margin, p.ny - margin), slice(margin, p.nx - margin))
+    return np.array([ux[w].mean(), uy[w].mean()])
 
 
-def keff_direct(kappa_patch, tau: float, eps: float, nu: float, g: float = 1e-6) -> np.ndarray:
+def keff_direct(kappa_patch, tau: float, eps: float, nu: float, g: float = 1e-6,
+                margin: int = 0) -> np.ndarray:
     """Eq. tensor-kappa from the exact steady states of the two periodic local
-    runs; returns [kxx, kxy, kyx, kyy]."""
+    runs; returns [kxx, kxy, kyx, kyy]. margin > 0 averages the velocity over
+    the inner window only (see steady_mean_velocity)."""
     k = np.ascontiguousarray(kappa_patch, dtype=np.float64)
     ny, nx = k.shape
+    if margin < 0 or nx - 2 * margin < 1 or ny - 2 * margin < 1:
+        raise ValueError("margin leaves no inner window")
     p = O.Params(nx=nx, ny=ny, tau=tau, eps=eps, nu=nu)
-    u1 = steady_mean_velocity(p, k, (g, 0.0))
-    u2 = steady_mean_velocity(p, k, (0.0, g))
+    u1 = steady_mean_velocity(p, k, (g, 0.0), margin=margin)
+    u2 = steady_mean_velocity(p, k, (0.0, g), margin=margin)
     return np.array([nu * u1[0] / g, nu * u2[0] / g, nu * u1[1] / g, nu * u2[1] / g])

@@ -408,6 +408,70 @@ def test_keff_symmetries():
     assert np.allclose(_keff(k, g=1e-4), base, rtol=0, atol=1e-6 * base[0])
 
 
+# ---------------------------------------------------------------------------
+# Oversampling: the mean velocity over the inner window [m, S - m)^2 only
+# ---------------------------------------------------------------------------
+
+
+def _layers(widths_vals, roll, S):
+    kx = np.roll(np.concatenate([np.full(w, v) for w, v in widths_vals]), roll)
+    assert kx.size == S
+    return kx, np.ascontiguousarray(np.tile(kx, (S, 1)))
+
+
+@pytest.mark.parametrize("margin", [0, 3, 5, 9])
+def test_window_parallel_layers_local_darcy_law(margin):
+    """Flow along layers (kappa varies with x only) at tau = 1/2, i.e. no
+    Brinkman viscosity: Darcy's law then holds point by point, u_y(x) =
+    kappa(x) G / nu, so the window mean gives the arithmetic mean of kappa
+    over the window's columns [m, S - m). The layers are placed off-centre, so
+    a window shifted or clipped by one column, or applied to rows instead,
+    changes the value. (The scheme reproduces the local law exactly for
+    layers at least four cells wide; Table 2 uses ten.)"""
+    S = 24
+    kx, k = _layers([(6, 1.0), (6, 7.0), (6, 3.0), (6, 20.0)], 3, S)
+    ke = DS.keff_direct(k, 0.5, 0.4, 0.1, 1e-9, margin=margin)
+    assert ke[3] == pytest.approx(kx[margin:S - margin].mean(), rel=1e-8)
+    assert abs(ke[1]) < 1e-7 * ke[0] and abs(ke[2]) < 1e-7 * ke[0]
+
+
+@pytest.mark.parametrize("margin", [0, 4, 7])
+@pytest.mark.parametrize("tau", [0.5, 0.8])
+def test_window_perpendicular_layers_harmonic_mean(tau, margin):
+    """Flow across the layers: mass conservation in 1-D makes the flux the
+    same in every column, so every window gives the harmonic mean of kappa
+    over the whole period (Table 1's closed form). Pins the division by the
+    window's own cell count."""
+    S = 16
+    kx, k = _layers([(4, 1.0), (4, 7.0), (4, 3.0), (4, 20.0)], 1, S)
+    ke = DS.keff_direct(k, tau, 0.4, 0.1, 1e-9, margin=margin)
+    assert ke[0] == pytest.approx(1.0 / np.mean(1.0 / kx), rel=1e-7)
+
+
+def test_window_symmetries_and_full_window():
+    """The window [m, S - m)^2 is mapped onto itself by the square's
+    symmetries, so the windowed tensor keeps the symmetries of the full one
+    (transpose swaps the axes, a mirror flips the off-diagonal sign); a
+    window off by one at one end breaks them. margin 0 is the plain mean.
+    A small drive (1e-9): the density varies at first order in G, which the
+    full-domain mean cancels but a window does not, so a mirror (which
+    reverses the drive) agrees only to O(G)."""
+    g = 1e-9
+    rng = np.random.default_rng(21)
+    k = np.exp(1.2 * rng.standard_normal((13, 13)))
+    base = _keff(k, g=g)
+    assert np.allclose(DS.keff_direct(k, 0.8, 0.4, 0.1, g, margin=0), base, rtol=1e-12)
+    w = DS.keff_direct(k, 0.8, 0.4, 0.1, g, margin=3)
+    assert np.max(np.abs(w - base)) > 1e-3 * base[0]   # the window does change K
+    t = DS.keff_direct(k.T.copy(), 0.8, 0.4, 0.1, g, margin=3)
+    assert np.allclose(t[[3, 2, 1, 0]], w, rtol=1e-8, atol=1e-12)
+    m = DS.keff_direct(k[:, ::-1].copy(), 0.8, 0.4, 0.1, g, margin=3)
+    assert np.allclose(m[[0, 3]], w[[0, 3]], rtol=1e-7)
+    assert np.allclose(m[[1, 2]], -w[[1, 2]], rtol=0, atol=1e-7 * w[0])
+    with pytest.raises(ValueError):
+        DS.keff_direct(k, 0.8, 0.4, 0.1, 1e-6, margin=7)
+
+
 def test_rho0_independence():
     rng = np.random.default_rng(8)
     k = np.exp(rng.standard_normal((8, 9)))
