@@ -153,6 +153,12 @@ typedef struct {
                              LBM_F64: FP64 state and arithmetic, needed where a
                              step moves the state by less than half an FP32
                              ulp (tau near 1/2 with weak drag) */
+    int32_t avg_margin;   /* oversampling (an addition to the paper, which
+                             names it as a treatment for high contrast): the
+                             mean velocity, for the convergence test and for
+                             Eq. tensor-kappa, is taken over the inner window
+                             [m, side - m)^2 only; 0 = the whole patch. Every
+                             side must exceed 2 m. */
 } lbm_local_params;
 
 /* One row of the tile table: how items of side `side` are laid out on a

@@ -79,6 +79,7 @@ struct LocalArgs {
     double tol;
     int check_every;
     int max_steps;
+    int margin;                          // cells left out of the average at each side
 };
 
 __device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -295,8 +296,13 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                     const double jy = (fd[2] - fd[4]) + ((fd[5] + fd[6]) - (fd[7] + fd[8]));
                     const double rho = 1.0 + dr;
                     const double D = (double)Dc[k];
-                    sx += D * (jx + hegx_d * rho) / rho;
-                    sy += D * (jy + hegy_d * rho) / rho;
+                    // oversampling: only the inner window enters the average
+                    const int x = xy[k] & 255, y = xy[k] >> 8;
+                    const int m = a.margin;
+                    if (x >= m && x < S - m && y >= m && y < S - m) {
+                        sx += D * (jx + hegx_d * rho) / rho;
+                        sy += D * (jy + hegy_d * rho) / rho;
+                    }
                 }
             }
         }
@@ -314,7 +320,8 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                 tx += red[w0 + w][0];
                 ty += red[w0 + w][1];
             }
-            const double ux = tx / S2, uy = ty / S2;
+            const double inner = (double)(S - 2 * a.margin) * (double)(S - 2 * a.margin);
+            const double ux = tx / inner, uy = ty / inner;
             int flag = -2;  // -2: keep going
             if (!isfinite(ux) || !isfinite(uy)) {
                 flag = 2;
@@ -449,6 +456,7 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
         return set_error(LBM_EINVAL, std::string(fn) + "max_steps must lie in [1, 2^30]");
     if (lp->pop_dtype != LBM_F32_SHIFTED && lp->pop_dtype != LBM_F64)
         return set_error(LBM_EINVAL, std::string(fn) + "unknown pop_dtype");
+    if (lp->avg_margin < 0) return set_error(LBM_EINVAL, std::string(fn) + "avg_margin must be >= 0");
     if (n_patches < 0) return set_error(LBM_EINVAL, std::string(fn) + "n_patches < 0");
     if (n_patches == 0) return LBM_OK;
     if (!h_x0 || !h_y0 || !h_side || !h_drive_mask || !d_kappa_field || !d_keff)
@@ -469,6 +477,8 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     for (int i = 0; i < n_patches; ++i) {
         if (h_side[i] < 1 || h_side[i] > kMaxSide)
             return set_error(LBM_EINVAL, std::string(fn) + "patch side must lie in [1, 64]");
+        if (h_side[i] - 2 * lp->avg_margin < 1)
+            return set_error(LBM_EINVAL, std::string(fn) + "avg_margin leaves no inner window");
         if (h_drive_mask[i] < 0 || h_drive_mask[i] > 3)
             return set_error(LBM_EINVAL, std::string(fn) + "drive mask must be 0..3");
     }
@@ -564,6 +574,7 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     a.nu_over_g = lp->nu / lp->g;
     a.tol = lp->tol;
     a.check_every = lp->check_every;
+    a.margin = lp->avg_margin;
     const int64_t ms = (lp->max_steps + lp->check_every - 1) / lp->check_every * lp->check_every;
     a.max_steps = (int)std::min<int64_t>(ms, (int64_t)1 << 30);
     // One persistent launch for all classes (largest side first, so small

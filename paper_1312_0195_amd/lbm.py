@@ -53,7 +53,7 @@ class lbm_local_params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("eps", ctypes.c_double), ("nu", ctypes.c_double),
                 ("g", ctypes.c_double), ("tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("max_steps", ctypes.c_int64),
-                ("pop_dtype", ctypes.c_int32)]
+                ("pop_dtype", ctypes.c_int32), ("avg_margin", ctypes.c_int32)]
 
 
 class lbm_local_tile(ctypes.Structure):
@@ -398,7 +398,8 @@ class LocalResult:
 
 def local_keff(kappa_field, x0, y0, side, tau, eps, nu, g=1e-6, tol=1e-6, check_every=100,
                max_steps=200000, drive_mask=None, tiles=None, block_threads=0, device="cuda",
-               kappa_dev=None, use_tuned=True, pop_dtype=LBM_F32_SHIFTED) -> LocalResult:
+               kappa_dev=None, use_tuned=True, pop_dtype=LBM_F32_SHIFTED,
+               avg_margin=0) -> LocalResult:
     """Run lbm_local_keff on a field (host array or device tensor) and return
     host results. Without explicit tiles, the autotuned table is used when
     one exists (see paper_1312_0195_amd.autotune)."""
@@ -416,7 +417,7 @@ def local_keff(kappa_field, x0, y0, side, tau, eps, nu, g=1e-6, tol=1e-6, check_
     nbytes = lbm_local_workspace_bytes(n)
     ws = _workspace(nbytes, dev)
     lp = lbm_local_params(float(tau), float(eps), float(nu), float(g), float(tol),
-                          int(check_every), int(max_steps), int(pop_dtype))
+                          int(check_every), int(max_steps), int(pop_dtype), int(avg_margin))
     dm = np.full(n, 3, np.int32) if drive_mask is None else drive_mask
     lbm_local_keff(lp, x0, y0, side, dm, kd, keff, steps, flags, tiles, block_threads, ws,
                    nbytes)

@@ -11,7 +11,13 @@
 The comparison metric is the relative L2 difference of the velocity fields on
 the coarse grid. Every step runs in the HIP library; torch holds the buffers.
 
-    python -m paper_1312_0195_amd.upscale [--n 4096] [--r 64] [--channels]
+Oversampling (the paper names it as a remedy for high contrast and channels,
+without details): the local problem of a coarse cell runs on a periodic
+window of side r + 2m centred on the cell, and only the cell's own r x r
+block enters the mean velocity (lbm_local_keff's avg_margin), so the
+artificial periodic boundary sits m cells away from the cells averaged.
+
+    python -m paper_1312_0195_amd.upscale [--n 4096] [--r 64] [--channels] [--margins 0,8,16]
 
 runs the upscaling workload (log-normal K, sigma 2, correlation length
 64 n / 4096, periodic; optionally with high-permeability streaks) and prints
@@ -35,6 +41,7 @@ class UpscaleResult:
     rel_l2: float
     rel_l2_scalar: float
     rel_l2_geomean: float     # coarse run with the block geometric mean of kappa instead of K*
+    by_margin: dict           # oversampling margin -> rel. L2 of u (tensor, scalar), local seconds
     mean_err: float           # relative error of the domain-mean velocity, tensor K*
     t_local: float
     t_coarse: float
@@ -49,16 +56,19 @@ def _rel_l2(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
-def local_tensor(kappa_dev, r, tau, eps, nu, g, tol=1e-7):
-    """K_eff per r x r subdomain of a periodic field: [ncy, ncx, 4]."""
+def local_tensor(kappa_dev, r, tau, eps, nu, g, tol=1e-7, margin=0):
+    """K_eff per r x r subdomain of a periodic field: [ncy, ncx, 4]. With
+    margin m > 0 each local problem runs on the (r + 2m)-sided window centred
+    on its subdomain (wrapping around the field) and averages over the
+    subdomain only."""
     ny, nx = kappa_dev.shape
     ncy, ncx = ny // r, nx // r
     J, I = np.meshgrid(np.arange(ncy), np.arange(ncx), indexing="ij")
-    x0 = (I.ravel() * r).astype(np.int32)
-    y0 = (J.ravel() * r).astype(np.int32)
-    side = np.full(x0.shape, r, np.int32)
+    x0 = ((I.ravel() * r - margin) % nx).astype(np.int32)
+    y0 = ((J.ravel() * r - margin) % ny).astype(np.int32)
+    side = np.full(x0.shape, r + 2 * margin, np.int32)
     res = L.local_keff(None, x0, y0, side, tau, eps, nu, g, tol=tol, check_every=100,
-                       max_steps=2_000_000, kappa_dev=kappa_dev)
+                       max_steps=2_000_000, kappa_dev=kappa_dev, avg_margin=margin)
     return res.keff.reshape(ncy, ncx, 4), bool((res.flags == 0).all())
 
 
@@ -115,7 +125,7 @@ def block_average(u_dev, r):
 
 def run(kappa, r, tau=0.8, eps=0.4, nu=0.1, g=1e-6, fine_tol=1e-7, fine_max_steps=2_000_000,
         fine_check=1000, coarse_tol=1e-7, verbose=False, coarse_check=100,
-        coarse_max_steps=4_000_000) -> UpscaleResult:
+        coarse_max_steps=4_000_000, margins=(0,)) -> UpscaleResult:
     import torch
     kd = torch.as_tensor(np.ascontiguousarray(kappa)).cuda()
     torch.cuda.synchronize()
@@ -137,6 +147,20 @@ def run(kappa, r, tau=0.8, eps=0.4, nu=0.1, g=1e-6, fine_tol=1e-7, fine_max_step
     kg = np.stack([gm, 0 * gm, 0 * gm, gm], axis=-1)
     u_cg, _, _ = coarse_solve(kappa.shape, kg, r, tau, eps, nu, g, L.LBM_KEFF_SCALAR, coarse_tol,
                               coarse_max_steps, check_every=coarse_check)
+    over = {}
+    for m in margins:
+        if m == 0:
+            continue
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        km, okm = local_tensor(kd, r, tau, eps, nu, g, margin=m)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ut, _, _ = coarse_solve(kappa.shape, km, r, tau, eps, nu, g, L.LBM_KEFF_TENSOR, coarse_tol,
+                                coarse_max_steps, check_every=coarse_check)
+        us, _, _ = coarse_solve(kappa.shape, km, r, tau, eps, nu, g, L.LBM_KEFF_SCALAR, coarse_tol,
+                                coarse_max_steps, check_every=coarse_check)
+        over[m] = (ut, us, tb - ta, okm)
     if verbose:
         print(f"local problems {t1 - t0:.2f} s, coarse solves {t3 - t1:.2f} s", flush=True)
     u_f, f_steps, f_st, solver = fine_solve(kappa, tau, eps, nu, g, fine_tol, fine_max_steps,
@@ -148,8 +172,14 @@ def run(kappa, r, tau=0.8, eps=0.4, nu=0.1, g=1e-6, fine_tol=1e-7, fine_max_step
     u_avg = block_average(u_f, r)
     solver.close()
     mc, mf = u_c.mean(axis=(1, 2)), u_avg.mean(axis=(1, 2))
+    by_margin = {0: dict(rel_l2_tensor=_rel_l2(u_c, u_avg), rel_l2_scalar=_rel_l2(u_cs, u_avg),
+                         t_local_s=t1 - t0, local_flags_ok=ok)}
+    for m, (ut, us, tl, okm) in over.items():
+        by_margin[m] = dict(rel_l2_tensor=_rel_l2(ut, u_avg), rel_l2_scalar=_rel_l2(us, u_avg),
+                            t_local_s=tl, local_flags_ok=okm)
     return UpscaleResult(keff, u_c, u_avg, _rel_l2(u_c, u_avg), _rel_l2(u_cs, u_avg),
-                         _rel_l2(u_cg, u_avg), float(np.linalg.norm(mc - mf) / np.linalg.norm(mf)),
+                         _rel_l2(u_cg, u_avg), by_margin,
+                         float(np.linalg.norm(mc - mf) / np.linalg.norm(mf)),
                          t1 - t0, t2 - t1, t4 - t3, f_steps, f_st, c_steps, ok)
 
 
@@ -168,12 +198,15 @@ def main():
                     help="coarse steps between checks; the fine grid checks every r times "
                          "as many steps, the same physical time")
     ap.add_argument("--fine-max-steps", type=int, default=2_000_000)
+    ap.add_argument("--margins", default="0",
+                    help="comma-separated oversampling margins m (r + 2m <= 64)")
     args = ap.parse_args()
+    margins = tuple(int(v) for v in args.margins.split(","))
     L.lib()
     w = I.workload_upscale(seed=args.seed, n=args.n, channels=args.channels)
     res = run(w["kappa"], args.r, fine_tol=args.tol, fine_check=args.coarse_check * args.r,
               fine_max_steps=args.fine_max_steps, coarse_tol=args.tol,
-              coarse_check=args.coarse_check, verbose=True)
+              coarse_check=args.coarse_check, verbose=True, margins=margins)
     print(json.dumps(dict(
         n=args.n, r=args.r, channels=args.channels, seed=args.seed,
         rel_l2_tensor=res.rel_l2, rel_l2_scalar=res.rel_l2_scalar,
@@ -183,6 +216,7 @@ def main():
         fine_steps=res.fine_steps, fine_status=res.fine_status, coarse_steps=res.coarse_steps,
         tol=args.tol, coarse_check=args.coarse_check, fine_check=args.coarse_check * args.r,
         local_flags_ok=res.local_flags_ok,
+        oversampling={str(m): v for m, v in res.by_margin.items()},
         max_abs_kxy_over_kxx=float(np.max(np.abs(res.keff[..., 1]) / res.keff[..., 0])))),
         flush=True)
 

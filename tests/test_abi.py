@@ -92,6 +92,19 @@ def test_local_rejects_unknown_pop_dtype_on_host():
     assert st == L.LBM_EINVAL
 
 
+def test_local_rejects_bad_avg_margin_on_host():
+    one = (ctypes.c_int32 * 1)(0)
+    side = (ctypes.c_int32 * 1)(8)
+    mask = (ctypes.c_int32 * 1)(3)
+    fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: validation fails first
+    for margin in (-1, 4, 9):          # side 8 leaves no inner window from m = 4 on
+        lp = L.lbm_local_params(0.8, 0.4, 0.1, 1e-6, 1e-6, 100, 1000, L.LBM_F32_SHIFTED, margin)
+        st = L.lib().lbm_local_keff(ctypes.byref(lp), 1, one, one, side, mask, fake, 8, 8, fake,
+                                    None, None, None, 0, 0, fake, 1 << 20, None)
+        assert st == L.LBM_EINVAL, margin
+        assert b"avg_margin" in L.lib().lbm_last_error()
+
+
 def test_cnn_forward_rejects_bad_n_sym_on_host():
     fake = ctypes.c_void_p(256 * 1024)
     for n_sym in (0, 9):

@@ -170,3 +170,42 @@ def test_local_f64_state_reaches_fixed_point_where_f32_stalls(L):
     with pytest.raises(L.LbmError):   # side 48 does not fit 4 cells per thread at 512 threads
         L.local_keff(field, one, one, np.array([48], np.int32), TAU, EPS, NU, G,
                      pop_dtype=L.LBM_F64)
+
+
+@pytest.mark.parametrize("pop_dtype", ["f32", "f64"])
+def test_local_oversampling_inner_window(L, pop_dtype):
+    """avg_margin m: the mean velocity of Eq. tensor-kappa (and the
+    convergence test) is taken over the inner window [m, side - m)^2 of each
+    patch only. Against the oracle's exact fixed point with the same window,
+    several margins per side, odd and even windows, wrapped origins."""
+    pd = L.LBM_F32_SHIFTED if pop_dtype == "f32" else L.LBM_F64
+    tol, keff_tol = (GPU_TOL, KEFF_TOL) if pop_dtype == "f32" else (1e-11, 1e-7)
+    field = I.lognormal_kappa(128, 96, 1.0, 6.0, seed=9)
+    sides = np.array([32, 24, 17, 13, 30], np.int32)
+    x0 = np.array([0, 120, 37, 64, 99], np.int32)
+    y0 = np.array([0, 90, 11, 50, 70], np.int32)
+    for margin in (1, 4, 6):
+        r = L.local_keff(field, x0, y0, sides, TAU, EPS, NU, G, tol=tol, check_every=100,
+                         max_steps=2_000_000, pop_dtype=pd, avg_margin=margin)
+        assert (r.flags == 0).all(), (margin, r.flags)
+        for i, s in enumerate(sides):
+            ko = DS.keff_direct(I.cut_patch(field, x0[i], y0[i], s), TAU, EPS, NU, G, margin=margin)
+            scale = max(abs(ko[0]), abs(ko[3]))
+            err = np.max(np.abs(r.keff[i] - ko)) / scale
+            assert err < keff_tol, (margin, s, r.keff[i], ko, err)
+
+
+def test_local_oversampling_layered_closed_form(L):
+    """Layers along y at tau = 1/2 (no Brinkman viscosity): Darcy's law holds
+    point by point, so with a margin K_yy is the arithmetic mean of kappa over
+    the window's columns and K_xx the harmonic mean over the whole period."""
+    kx = np.roll(np.repeat([1.0, 7.0, 3.0, 20.0], 6), 3)
+    field = np.ascontiguousarray(np.tile(kx, (24, 1)))
+    zero = np.zeros(1, np.int32)
+    for m in (0, 5, 9):
+        r = L.local_keff(field, zero, zero, np.array([24], np.int32), 0.5, EPS, NU, 1e-9,
+                         tol=1e-12, check_every=200, max_steps=4_000_000, pop_dtype=L.LBM_F64,
+                         avg_margin=m)
+        assert (r.flags == 0).all()
+        assert r.keff[0, 3] == pytest.approx(kx[m:24 - m].mean(), rel=1e-7)
+        assert r.keff[0, 0] == pytest.approx(1.0 / np.mean(1.0 / kx), rel=1e-6)
