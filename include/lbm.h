@@ -312,6 +312,65 @@ lbm_status lbm_cnn_train_step(float *d_params, float *d_adam_m, float *d_adam_v,
                               float *d_loss, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Three-dimensional fine grid: the same step on the D3Q19 lattice (Sec. 2:
+ * three-dimensional problems use D3Q19, with their own velocities and
+ * weights and the algorithm unchanged): Eqs. explicit-u-in-Guo,
+ * final-ueq-of-S-C, feq and f-evolution-of-S-C with three velocity
+ * components, a scalar permeability per cell and a uniform force.
+ *
+ * Population order, also the layout of lbm3d_get/set_populations: 0 rest;
+ * 1..6: +x, -x, +y, -y, +z, -z (weight 1/18); 7..10: +x+y, -x-y, +x-y, -x+y;
+ * 11..14: +x+z, -x-z, +x-z, -x+z; 15..18: +y+z, -y-z, +y-z, -y+z (1/36);
+ * rest 1/3. Cells are x-fastest: index (z ny + y) nx + x.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t nx, ny, nz;   /* nx ny nz below 2^31 - 65536 */
+    double tau;           /* >= 1/2 */
+    double eps, nu, rho0; /* as in lbm_params */
+    double gx, gy, gz;    /* uniform body force per unit mass G */
+    int32_t walls_z;      /* 0: periodic in z; 1: halfway bounce-back walls half a
+                             cell below plane 0 and above plane nz-1 (x and y
+                             are periodic) */
+    int32_t pop_dtype;    /* LBM_F32_SHIFTED or LBM_F64 */
+} lbm3d_params;
+
+typedef struct lbm3d_handle lbm3d_handle;
+
+/* Bytes of workspace lbm3d_init needs (0 if the parameters are invalid). */
+size_t lbm3d_workspace_bytes(const lbm3d_params *p);
+
+/* Set up a solver at the rest state f_a = w_a rho0.
+ *   d_kappa : device FP64 [nz][ny][nx], read once; values must be > 0
+ *             (+inf: no drag), else LBM_EINVAL.
+ *   d_ws    : device workspace, >= lbm3d_workspace_bytes(p), 256-byte
+ *             aligned, alive until lbm3d_destroy (caller-owned).
+ * Synchronises the stream (the permeability check is read back). */
+lbm_status lbm3d_init(lbm3d_handle **h, const lbm3d_params *p, const double *d_kappa, void *d_ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Advance up to max_steps steps, one launch per step. check_every, tol,
+ * steps_done and mean_u (three components, FP64 volume average of the flow
+ * velocity) behave as in lbm_step. */
+lbm_status lbm3d_step(lbm3d_handle *h, int64_t max_steps, double tol, int32_t check_every,
+                      int64_t *steps_done, double mean_u[3]);
+
+/* Flow velocity and density of the current state.
+ *   d_u   : device FP64 [3][nz][ny][nx] (u_x, u_y, u_z planes), or NULL
+ *   d_rho : device FP64 [nz][ny][nx], or NULL (not both NULL). */
+lbm_status lbm3d_fields(lbm3d_handle *h, double *d_u, double *d_rho);
+
+/* Full pre-collision populations, device FP64 [19][nz][ny][nx] (order above). */
+lbm_status lbm3d_get_populations(lbm3d_handle *h, double *d_f);
+
+/* Replace the state by d_f (same layout); the step counter is kept. */
+lbm_status lbm3d_set_populations(lbm3d_handle *h, const double *d_f);
+
+int64_t lbm3d_steps_total(const lbm3d_handle *h);
+
+void lbm3d_destroy(lbm3d_handle *h);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
 

@@ -144,7 +144,8 @@ def step_at(p: Params3, kappa, f, cells, g=(0.0, 0.0, 0.0)) -> np.ndarray:
     E, _, OPP = lattice()
     cells = np.asarray(cells, dtype=np.int64)
     out = np.empty((len(cells), 19))
-    kappa = np.asarray(kappa, dtype=np.float64)
+    # f and kappa are only indexed cell by cell ([z, y, x]), so any object
+    # with that lookup serves (e.g. the gathered neighbourhoods of samples)
     for i, (x, y, z) in enumerate(cells):
         for a in range(19):
             sx, sy, sz = x - E[a, 0], y - E[a, 1], z - E[a, 2]
@@ -152,7 +153,7 @@ def step_at(p: Params3, kappa, f, cells, g=(0.0, 0.0, 0.0)) -> np.ndarray:
             if p.walls_z and not (0 <= sz < p.nz):
                 sx, sy, sz, pop = x, y, z, OPP[a]
             sx, sy, sz = sx % p.nx, sy % p.ny, sz % p.nz
-            cell_f = f[sz, sy, sx][None, None, None, :]
-            cell_k = kappa[sz, sy, sx].reshape(1, 1, 1)
+            cell_f = np.asarray(f[sz, sy, sx], dtype=np.float64).reshape(1, 1, 1, 19)
+            cell_k = np.full((1, 1, 1), float(kappa[sz, sy, sx]))
             out[i, a] = collide(p, cell_k, cell_f, g)[0, 0, 0, pop]
     return out

@@ -50,6 +50,36 @@ def grf_logk(nx: int, ny: int, sigma: float, corr_len: float, seed: int) -> np.n
     return np.ascontiguousarray(z)
 
 
+def grf_logk3(nx: int, ny: int, nz: int, sigma: float, corr_len: float, seed: int) -> np.ndarray:
+    """Three-dimensional counterpart of :func:`grf_logk`, shape [nz, ny, nx]
+    (x fastest), same recipe (FP32 white noise and transforms to keep the
+    memory of large grids modest; the result is FP64)."""
+    if nx <= 0 or ny <= 0 or nz <= 0:
+        raise ValueError("grid sides must be positive")
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((nz, ny, nx), dtype=np.float32)
+    kz = 2.0 * np.pi * np.fft.fftfreq(nz)
+    ky = 2.0 * np.pi * np.fft.fftfreq(ny)
+    kx = 2.0 * np.pi * np.fft.rfftfreq(nx)                # real transform: x halved
+    wf = np.fft.rfftn(w, axes=(0, 1, 2))
+    k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    wf *= np.exp(-0.25 * corr_len * corr_len * k2).astype(np.float32)
+    del k2
+    z = np.fft.irfftn(wf, s=(nz, ny, nx), axes=(0, 1, 2)).astype(np.float64)
+    del wf
+    z -= z.mean()
+    sd = z.std()
+    if sd > 0:
+        z *= sigma / sd
+    return np.ascontiguousarray(z)
+
+
+def lognormal_kappa3(nx: int, ny: int, nz: int, sigma: float, corr_len: float,
+                     seed: int) -> np.ndarray:
+    """K = exp(Z) with Z from :func:`grf_logk3`, [nz, ny, nx]."""
+    return np.exp(grf_logk3(nx, ny, nz, sigma, corr_len, seed))
+
+
 def lognormal_kappa(nx: int, ny: int, sigma: float, corr_len: float, seed: int) -> np.ndarray:
     """K = exp(Z) with Z from :func:`grf_logk` (lattice units, median 1)."""
     return np.exp(grf_logk(nx, ny, sigma, corr_len, seed))
@@ -257,6 +287,14 @@ def workload_upscale(seed: int = 1, n: int = 4096, channels: bool = False) -> di
     if channels:
         k = channelize(k, 0.05, 8, 1e3, seed)
     return dict(nx=n, ny=n, kappa=k, walls_y=0, **COMMON)
+
+
+def workload_d3q19(seed: int = 1, n: int = 256) -> dict:
+    """D3Q19 fine grid: n^3 (256^3 by default), sigma 1.5, correlation length
+    16 n / 256, walls in z (x and y periodic), the same physics as the
+    two-dimensional fine workload, force along x."""
+    return dict(nx=n, ny=n, nz=n, kappa=lognormal_kappa3(n, n, n, 1.5, 16.0 * n / 256.0, seed),
+                walls_z=1, tau=0.8, eps=0.4, nu=0.1, g=(1e-6, 0.0, 0.0))
 
 
 def surrogate_fields(n_fields: int, seed: int, n: int = 256,

@@ -32,6 +32,8 @@ EXPORTS = (
     "lbm_last_error",
     "lbm_cnn_param_count", "lbm_cnn_workspace_bytes", "lbm_cnn_forward", "lbm_cnn_gradients",
     "lbm_cnn_train_step", "lbm_patch_stats",
+    "lbm3d_workspace_bytes", "lbm3d_init", "lbm3d_step", "lbm3d_fields", "lbm3d_get_populations",
+    "lbm3d_set_populations", "lbm3d_steps_total", "lbm3d_destroy",
 )
 
 
@@ -47,6 +49,13 @@ class lbm_params(ctypes.Structure):
                 ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("walls_y", ctypes.c_int32),
                 ("pop_dtype", ctypes.c_int32), ("perm_kind", ctypes.c_int32),
                 ("scheme", ctypes.c_int32)]
+
+
+class lbm3d_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("eps", ctypes.c_double), ("nu", ctypes.c_double),
+                ("rho0", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+                ("gz", ctypes.c_double), ("walls_z", ctypes.c_int32), ("pop_dtype", ctypes.c_int32)]
 
 
 class lbm_local_params(ctypes.Structure):
@@ -96,6 +105,24 @@ def lib():
     L.lbm_steps_total.restype = ctypes.c_int64
     L.lbm_destroy.argtypes = [_vp]
     L.lbm_destroy.restype = None
+    p3 = ctypes.POINTER(lbm3d_params)
+    L.lbm3d_workspace_bytes.argtypes = [p3]
+    L.lbm3d_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm3d_init.argtypes = [ctypes.POINTER(_vp), p3, _vp, _vp, ctypes.c_size_t, _vp]
+    L.lbm3d_init.restype = ctypes.c_int
+    L.lbm3d_step.argtypes = [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_int64), _dp]
+    L.lbm3d_step.restype = ctypes.c_int
+    for name in ("lbm3d_fields",):
+        getattr(L, name).argtypes = [_vp, _vp, _vp]
+        getattr(L, name).restype = ctypes.c_int
+    for name in ("lbm3d_get_populations", "lbm3d_set_populations"):
+        getattr(L, name).argtypes = [_vp, _vp]
+        getattr(L, name).restype = ctypes.c_int
+    L.lbm3d_steps_total.argtypes = [_vp]
+    L.lbm3d_steps_total.restype = ctypes.c_int64
+    L.lbm3d_destroy.argtypes = [_vp]
+    L.lbm3d_destroy.restype = None
     L.lbm_local_max_side.argtypes = []
     L.lbm_local_max_side.restype = ctypes.c_int32
     L.lbm_local_workspace_bytes.argtypes = [ctypes.c_int32]
@@ -210,6 +237,48 @@ def lbm_steps_total(h) -> int:
 
 def lbm_destroy(h) -> None:
     lib().lbm_destroy(h)
+
+
+def lbm3d_workspace_bytes(p: lbm3d_params) -> int:
+    return int(lib().lbm3d_workspace_bytes(ctypes.byref(p)))
+
+
+def lbm3d_init(p: lbm3d_params, d_kappa, d_ws, ws_bytes: int, stream=None) -> ctypes.c_void_p:
+    h = _vp()
+    st = lib().lbm3d_init(ctypes.byref(h), ctypes.byref(p), _ptr(d_kappa), _ptr(d_ws), ws_bytes,
+                          _stream(stream))
+    _raise(st, "lbm3d_init")
+    return h
+
+
+def lbm3d_step(h, max_steps: int, tol: float = 0.0, check_every: int = 0):
+    """Returns (status, steps_done, mean_u[3]), as lbm_step."""
+    steps = ctypes.c_int64(0)
+    mu = (ctypes.c_double * 3)()
+    st = lib().lbm3d_step(h, int(max_steps), float(tol), int(check_every), ctypes.byref(steps), mu)
+    if st not in (LBM_OK, LBM_ENOTCONV, LBM_ENONFINITE):
+        _raise(st, "lbm3d_step")
+    return st, steps.value, np.array([mu[0], mu[1], mu[2]])
+
+
+def lbm3d_fields(h, d_u, d_rho=None) -> None:
+    _raise(lib().lbm3d_fields(h, _ptr(d_u), _ptr(d_rho)), "lbm3d_fields")
+
+
+def lbm3d_get_populations(h, d_f) -> None:
+    _raise(lib().lbm3d_get_populations(h, _ptr(d_f)), "lbm3d_get_populations")
+
+
+def lbm3d_set_populations(h, d_f) -> None:
+    _raise(lib().lbm3d_set_populations(h, _ptr(d_f)), "lbm3d_set_populations")
+
+
+def lbm3d_steps_total(h) -> int:
+    return int(lib().lbm3d_steps_total(h))
+
+
+def lbm3d_destroy(h) -> None:
+    lib().lbm3d_destroy(h)
 
 
 def lbm_local_max_side() -> int:
@@ -387,6 +456,70 @@ class FineSolver:
             self.close()
         except Exception:
             pass
+
+
+class Solver3D:
+    """Owns the torch buffers of one lbm3d_handle (D3Q19 fine grid)."""
+
+    def __init__(self, p: lbm3d_params, kappa, device="cuda"):
+        import torch
+        self.p = p
+        self.device = torch.device(device)
+        k = torch.as_tensor(np.ascontiguousarray(kappa) if isinstance(kappa, np.ndarray) else kappa,
+                            dtype=torch.float64)
+        self.kappa = k.to(self.device).contiguous()
+        nbytes = lbm3d_workspace_bytes(p)
+        if nbytes == 0:
+            raise LbmError(LBM_EINVAL, "invalid parameters")
+        self.ws = _workspace(nbytes, self.device)
+        self.h = lbm3d_init(p, self.kappa, self.ws, nbytes)
+
+    def step(self, max_steps, tol=0.0, check_every=0):
+        return lbm3d_step(self.h, max_steps, tol, check_every)
+
+    def fields(self):
+        import torch
+        shape = (self.p.nz, self.p.ny, self.p.nx)
+        u = torch.empty((3,) + shape, dtype=torch.float64, device=self.device)
+        rho = torch.empty(shape, dtype=torch.float64, device=self.device)
+        lbm3d_fields(self.h, u, rho)
+        torch.cuda.synchronize(self.device)
+        return u, rho
+
+    def populations(self):
+        import torch
+        f = torch.empty((19, self.p.nz, self.p.ny, self.p.nx), dtype=torch.float64,
+                        device=self.device)
+        lbm3d_get_populations(self.h, f)
+        torch.cuda.synchronize(self.device)
+        return f
+
+    def set_populations(self, f):
+        import torch
+        f = torch.as_tensor(f, dtype=torch.float64).to(self.device).contiguous()
+        lbm3d_set_populations(self.h, f)
+        torch.cuda.synchronize(self.device)
+
+    @property
+    def steps_total(self):
+        return lbm3d_steps_total(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params3(nx, ny, nz, tau, eps, nu, rho0=1.0, g=(0.0, 0.0, 0.0), walls_z=0,
+                 pop_dtype=LBM_F32_SHIFTED) -> lbm3d_params:
+    return lbm3d_params(int(nx), int(ny), int(nz), float(tau), float(eps), float(nu), float(rho0),
+                        float(g[0]), float(g[1]), float(g[2]), int(walls_z), int(pop_dtype))
 
 
 @dataclass

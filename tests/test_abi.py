@@ -17,7 +17,7 @@ def _declared():
         if fn.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", fn)).read()
             txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-            names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt))
+            names |= set(re.findall(r"\b(lbm(?:3d)?_[a-z0-9_]+)\s*\(", txt))
     return names
 
 
@@ -103,6 +103,24 @@ def test_local_rejects_bad_avg_margin_on_host():
                                     None, None, None, 0, 0, fake, 1 << 20, None)
         assert st == L.LBM_EINVAL, margin
         assert b"avg_margin" in L.lib().lbm_last_error()
+
+
+def test_d3q19_params_validated_on_host():
+    ok = L.make_params3(64, 8, 8, 0.8, 0.4, 0.1)
+    assert L.lbm3d_workspace_bytes(ok) > 2 * 19 * 64 * 8 * 8 * 4
+    f64 = L.make_params3(64, 8, 8, 0.8, 0.4, 0.1, pop_dtype=L.LBM_F64)
+    assert L.lbm3d_workspace_bytes(f64) > L.lbm3d_workspace_bytes(ok)
+    for field, bad in (("nz", 0), ("tau", 0.49), ("eps", 0.0), ("nu", -1.0), ("walls_z", 2),
+                       ("pop_dtype", 7), ("gz", float("nan")), ("nx", 1 << 20)):
+        p = L.make_params3(64, 8, 8, 0.8, 0.4, 0.1)
+        setattr(p, field, bad)
+        if field == "nx":
+            p.ny, p.nz = 1 << 10, 1 << 10
+        assert L.lbm3d_workspace_bytes(p) == 0, field
+        h = ctypes.c_void_p()
+        fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: validation fails first
+        st = L.lib().lbm3d_init(ctypes.byref(h), ctypes.byref(p), fake, fake, 1 << 40, None)
+        assert st == L.LBM_EINVAL and not h.value, field
 
 
 def test_cnn_forward_rejects_bad_n_sym_on_host():
