@@ -7,15 +7,17 @@ D2Q9 BGK Brinkman LBM with the Shan-Chen velocity-shift force on a 2048 x 2048
 grid, log-normal permeability K = exp(Z) (Z a seeded periodic Gaussian random
 field, sigma 1.5, correlation length 32 cells), porosity 0.4, tau 0.8,
 nu = nu_eff = 0.1, g = 1e-6 along x, bounce-back walls in y, FP32 deviation
-populations. Steps run two per launch (temporal blocking through LDS); the
+populations. Steps run six per launch (temporal blocking through LDS); the
 volume-averaged velocity (FP64 reduction) is taken every 100 steps inside the
 timed region.
 
 Printed: one JSON line with MLUPS (value), the HBM roofline of the step kernel
 measured live with HIP events, the batched local K_eff throughput (patches/s)
 on the 4096 32 x 32 tiles of the same field plus 4096 mixed-size patches, the
-learned K_eff path (network + LBM fallback vs LBM alone, with its error), and
-the CPU oracle timed on a bounded sample of the same workload.
+learned K_eff path (network + LBM fallback vs LBM alone, with its error), the
+same step on the D3Q19 lattice (256^3) against the HBM roofline and a plain
+device copy, and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -174,6 +176,56 @@ def bench_surrogate(n_test=65536):
                 keff_rel_error_geometric_mean_p50=r["keff_error_geometric_mean_in_range"]["p50"])
 
 
+D3Q19_BYTES_PER_LU = 156  # 19 x 4 B read + 19 x 4 B written + 4 B drag coefficient
+
+
+def bench_d3q19(L, torch, n=256, steps=200, warmup=20):
+    """The step on the D3Q19 lattice: n^3 log-normal field (sigma 1.5), walls
+    in z, FP32 deviation populations, one launch per step; the kernel time
+    from HIP events over back-to-back launches, and a plain device copy of
+    the same byte count as the practical HBM ceiling."""
+    from paper_1312_0195_amd import inputs as I
+    w = I.workload_d3q19(n=n)
+    p = L.make_params3(n, n, n, w["tau"], w["eps"], w["nu"], 1.0, w["g"], w["walls_z"],
+                       L.LBM_F32_SHIFTED)
+    s = L.Solver3D(p, w["kappa"])
+    stream = torch.cuda.current_stream()
+    s.step(warmup, 0.0, 0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps, 0.0, 0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    st, _, mu = s.step(2, 0.0, 1)
+    assert st == L.LBM_OK and np.isfinite(mu).all()
+    s.close()
+    cells = n ** 3
+    gbs = D3Q19_BYTES_PER_LU * cells / (us * 1e-6) / 1e9
+    # plain copy moving the same bytes (half read, half written)
+    src = torch.empty(D3Q19_BYTES_PER_LU * cells // 8, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return dict(workload=f"{n}^3 D3Q19 Brinkman LBM, log-normal K (sigma 1.5, corr {16 * n // 256}), "
+                         f"tau 0.8, g 1e-6 along x, walls in z, FP32 deviation populations",
+                us_per_step=round(us, 2), mlups=round(cells / us, 1),
+                roofline={"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "kernel": "k3_step<float, walls>",
+                          "hbm_bytes_per_launch_algorithmic": D3Q19_BYTES_PER_LU * cells},
+                device_copy_gbs=round(copy_gbs, 1),
+                frac_of_device_copy=round(gbs / copy_gbs, 4))
+
+
 def cpu_baseline(kappa, steps):
     from oracle import oracle as O
     n = kappa.shape[0]
@@ -197,6 +249,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-local", action="store_true")
+    ap.add_argument("--no-d3q19", action="store_true")
+    ap.add_argument("--only-d3q19", action="store_true",
+                    help="run the D3Q19 leg alone (for profiling) and print its object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 302 MB device copy, the reference for HBM counters")
     args = ap.parse_args()
@@ -224,6 +279,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 4}), flush=True)
         del src, dst
+    if args.only_d3q19:
+        print(json.dumps({"d3q19": bench_d3q19(L, torch)}), flush=True)
+        return
     fine = bench_fine(L, torch, kappa, args.steps, args.warmup)
     ms_per_step = fine["event_ms"] / args.steps
     mlups = cells * args.steps / (fine["event_ms"] * 1e-3) / 1e6
@@ -274,6 +332,8 @@ def main():
         result["local_keff"] = bench_local(L, torch, kd)
     if not args.no_surrogate and not args.no_local:
         result["keff_surrogate"] = bench_surrogate()
+    if not args.no_d3q19:
+        result["d3q19"] = bench_d3q19(L, torch)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(kappa, args.cpu_steps)
     print(json.dumps(result), flush=True)

@@ -325,7 +325,7 @@ lbm_status lbm_cnn_train_step(float *d_params, float *d_adam_m, float *d_adam_v,
  * ------------------------------------------------------------------------- */
 
 typedef struct {
-    int32_t nx, ny, nz;   /* nx ny nz below 2^31 - 65536 */
+    int32_t nx, ny, nz;   /* (nx ny nz + 65536) x 4 B (FP32) or 8 B (FP64) below 4 GiB */
     double tau;           /* >= 1/2 */
     double eps, nu, rho0; /* as in lbm_params */
     double gx, gy, gz;    /* uniform body force per unit mass G */

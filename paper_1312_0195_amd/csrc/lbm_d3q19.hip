@@ -36,7 +36,7 @@ using lbm::hip_check;
 using lbm::wave_sum;
 
 constexpr int Q = 19;
-constexpr int kTX = 64, kTY = 4, kBlock3 = kTX * kTY;
+constexpr int kTX = 128, kTY = 2, kBlock3 = kTX * kTY;
 constexpr size_t kPlanePad = 16384;  // bytes between planes beyond their size
 
 __host__ __device__ constexpr int cx(int a)
@@ -84,7 +84,7 @@ __device__ __forceinline__ bool cell_of(int nx, int ny, int &x, int &y, int &z)
     const int ty = rest % nty;
     z = rest / nty;
     x = tx * kTX + (threadIdx.x & (kTX - 1));
-    y = ty * kTY + (threadIdx.x >> 6);
+    y = ty * kTY + (int)(threadIdx.x / kTX);
     return x < nx && y < ny;
 }
 
@@ -104,7 +104,12 @@ __device__ __forceinline__ void pull3(const R *__restrict__ in, size_t S, int nx
     const unsigned p0 = (unsigned)z * pn, pm = (unsigned)zm * pn, pp = (unsigned)zp * pn;
     const unsigned r0 = (unsigned)y * nx, rm = (unsigned)ym * nx, rp = (unsigned)yp * nx;
     const unsigned c = p0 + r0 + x;
-    auto ld = [&](int a, unsigned i) { return in[(size_t)a * S + i]; };
+    // plane base (uniform, in scalar registers) plus a 32-bit byte offset per
+    // lane: global loads in their scalar-base form, no 64-bit address adds
+    auto ld = [&](int a, unsigned i) {
+        const char *base = reinterpret_cast<const char *>(in + (size_t)a * S);
+        return *reinterpret_cast<const R *>(base + i * (unsigned)sizeof(R));
+    };
     f[0] = ld(0, c);
     f[1] = ld(1, p0 + r0 + xm);
     f[2] = ld(2, p0 + r0 + xp);
@@ -209,9 +214,10 @@ __global__ __launch_bounds__(kBlock3) void k3_step(Args3<R> a)
     double f[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) f[q] = (double)fr[q];
-    collide3(a, f, (double)a.coef[c]);
+    collide3(a, f, (double)*reinterpret_cast<const R *>(reinterpret_cast<const char *>(a.coef) + c * (unsigned)sizeof(R)));
 #pragma unroll
-    for (int q = 0; q < Q; ++q) a.fout[(size_t)q * a.stride + c] = (R)f[q];
+    for (int q = 0; q < Q; ++q)
+        *reinterpret_cast<R *>(reinterpret_cast<char *>(a.fout + (size_t)q * a.stride) + c * (unsigned)sizeof(R)) = (R)f[q];
 }
 
 // Flow velocity and density of the current state (FP64), and per-block FP64
@@ -365,8 +371,10 @@ bool params_ok(const lbm3d_params *p, std::string &why)
 {
     if (!p) { why = "params is NULL"; return false; }
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "nx, ny and nz must be >= 1"; return false; }
+    // byte offsets within a plane are 32-bit
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
-    if (n + 65536 >= ((int64_t)1 << 31)) { why = "grid too large (nx ny nz must be below 2^31 - 65536)"; return false; }
+    const int64_t elem = p->pop_dtype == LBM_F64 ? 8 : 4;
+    if ((n + 65536) * elem >= ((int64_t)1 << 32)) { why = "grid too large (nx ny nz times the population size must be below 4 GiB)"; return false; }
     if (!(p->tau >= 0.5) || !std::isfinite(p->tau)) { why = "tau must be finite and >= 0.5"; return false; }
     if (!(p->eps > 0.0 && p->eps <= 1.0)) { why = "eps must lie in (0, 1]"; return false; }
     if (!(p->nu > 0.0) || !std::isfinite(p->nu)) { why = "nu must be finite and > 0"; return false; }
