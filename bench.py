@@ -181,9 +181,9 @@ D3Q19_BYTES_PER_LU = 156  # 19 x 4 B read + 19 x 4 B written + 4 B drag coeffici
 
 def bench_d3q19(L, torch, n=256, steps=200, warmup=20):
     """The step on the D3Q19 lattice: n^3 log-normal field (sigma 1.5), walls
-    in z, FP32 deviation populations, one launch per step; the kernel time
+    in z, FP32 deviation populations, two steps per launch; the kernel time
     from HIP events over back-to-back launches, and a plain device copy of
-    the same byte count as the practical HBM ceiling."""
+    the same byte count (one pass of the state) as the HBM reference."""
     from paper_1312_0195_amd import inputs as I
     w = I.workload_d3q19(n=n)
     p = L.make_params3(n, n, n, w["tau"], w["eps"], w["nu"], 1.0, w["g"], w["walls_z"],
@@ -202,7 +202,8 @@ def bench_d3q19(L, torch, n=256, steps=200, warmup=20):
     assert st == L.LBM_OK and np.isfinite(mu).all()
     s.close()
     cells = n ** 3
-    gbs = D3Q19_BYTES_PER_LU * cells / (us * 1e-6) / 1e9
+    launch_us = 2 * us                       # two time steps per launch
+    gbs = D3Q19_BYTES_PER_LU * cells / (launch_us * 1e-6) / 1e9
     # plain copy moving the same bytes (half read, half written)
     src = torch.empty(D3Q19_BYTES_PER_LU * cells // 8, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -220,10 +221,14 @@ def bench_d3q19(L, torch, n=256, steps=200, warmup=20):
                 us_per_step=round(us, 2), mlups=round(cells / us, 1),
                 roofline={"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                          "kernel": "k3_step<float, walls>",
-                          "hbm_bytes_per_launch_algorithmic": D3Q19_BYTES_PER_LU * cells},
+                          "kernel": "k3_step2<walls> (2 time steps per launch)",
+                          "avg_launch_us": round(launch_us, 2),
+                          "hbm_bytes_per_launch_algorithmic": D3Q19_BYTES_PER_LU * cells,
+                          "single_step_hbm_equivalent_gbs":
+                              round(D3Q19_BYTES_PER_LU * cells / (us * 1e-6) / 1e9, 1)},
                 device_copy_gbs=round(copy_gbs, 1),
-                frac_of_device_copy=round(gbs / copy_gbs, 4))
+                single_step_equivalent_over_device_copy=round(
+                    D3Q19_BYTES_PER_LU * cells / (us * 1e-6) / 1e9 / copy_gbs, 4))
 
 
 def cpu_baseline(kappa, steps):

@@ -12,7 +12,7 @@
 // population from its upstream neighbour, collides in FP64 and stores, so
 // every population element is read once and written once per step:
 // 19 x 2 x 4 B + 4 B of drag coefficient = 156 B per lattice update (FP32).
-// The step is bound by HBM bandwidth; there is no temporal blocking here.
+// With FP32 state two steps run per launch (k3_step2, below), halving that.
 //
 // Population order (also the layout of lbm3d_get_populations): rest; +x, -x,
 // +y, -y, +z, -z; the diagonals of the xy plane (+x+y, -x-y, +x-y, -x+y), of
@@ -220,6 +220,203 @@ __global__ __launch_bounds__(kBlock3) void k3_step(Args3<R> a)
         *reinterpret_cast<R *>(reinterpret_cast<char *>(a.fout + (size_t)q * a.stride) + c * (unsigned)sizeof(R)) = (R)f[q];
 }
 
+// ---------------------------------------------------------------------------
+// Two time steps per launch (FP32 state): each workgroup owns an IX x IY tile
+// of (x, y) columns and a run of zc planes, and marches up z. For every
+// plane p it takes step 1 on the tile plus a one-cell halo, (IX + 2) x
+// (IY + 2) cells (pulled from HBM, collided in FP64, rounded to FP32 as a
+// stored step would be), into LDS, then step 2 on the IX x IY cells of plane
+// p - 1, pulling from the step-1 planes p - 2, p - 1 and p, and stores that
+// to HBM. The state passes through HBM once per two steps (156 B per two
+// lattice updates) and the result is bit-identical to two single steps.
+// Extra work: the halo cells and two step-1 planes per chunk.
+//
+// LDS keeps each population only as long as step 2 needs it: the in-plane
+// populations of the last two planes, the +z populations of the last three
+// (read by the plane above) and the -z populations of the last two (read by
+// the plane below, and by the bounce-back of the bottom plane): 43 planes of
+// the halo tile. The loads of the next plane's step 1 are issued before
+// step 2 and stay in flight across the barrier, which orders LDS operations
+// only.
+//
+// Tile 64 x 8 (66 x 10 with the halo: 29% extra step-1 cells), 512 threads,
+// 113.5 KB of LDS: one workgroup per CU. Measured on 256^3 against 32 x 8,
+// 30 x 6, 32 x 4, 64 x 4, 32 x 16, 62 x 6, 64 x 6, 96 x 4 and 128 x 4 tiles,
+// without the prefetch, and with z runs of 16 to 128 planes (all
+// bit-identical): 64 x 8 with runs of 128 planes was the fastest. The run
+// length zc is chosen per grid on the host (launch_step2).
+// ---------------------------------------------------------------------------
+constexpr int k2IX = 64, k2IY = 8, k2T = 512;
+
+// Barrier that orders LDS only: global loads in flight stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// populations by role in step 2: in the plane (0..4, 7..10), +z, -z
+__device__ constexpr int kIn[9] = {0, 1, 2, 3, 4, 7, 8, 9, 10};
+__device__ constexpr int kUp[5] = {5, 11, 14, 15, 18};
+__device__ constexpr int kDn[5] = {6, 12, 13, 16, 17};
+
+template <int IX, int IY, int T>
+struct Tile2 {
+    static constexpr int EX = IX + 2, EY = IY + 2, NE = EX * EY;  // halo tile
+    static constexpr int R1 = (NE + T - 1) / T;                    // step-1 cells per thread
+    static_assert(IX * IY <= T, "one step-2 cell per thread");
+    static_assert(R1 <= 2, "at most two step-1 cells per thread");
+};
+using Tl2 = Tile2<k2IX, k2IY, k2T>;
+
+template <bool WALLS>
+__global__ __launch_bounds__(k2T) void k3_step2(Args3<float> a, int zc)
+{
+    constexpr bool PF = true;
+    constexpr int IX = k2IX, IY = k2IY, T = k2T;
+    constexpr int EX = Tl2::EX, NE = Tl2::NE, R1 = Tl2::R1;
+    __shared__ float sin_[2][9][NE];  // in-plane populations, planes p - 1, p
+    __shared__ float sup[3][5][NE];   // +z populations, planes p - 2 .. p
+    __shared__ float sdn[2][5][NE];   // -z populations, planes p - 1, p
+    constexpr int kXcd = 8;
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int qq = nb / kXcd, rem = nb % kXcd;
+    const int k = bid % kXcd, slot = bid / kXcd;
+    const int t = k * qq + (k < rem ? k : rem) + slot;
+    const int ntx = (a.nx + IX - 1) / IX, nty = (a.ny + IY - 1) / IY;
+    const int tx = t % ntx, rest = t / ntx;
+    const int ty = rest % nty, tz = rest / nty;
+    const int x0 = tx * IX, y0 = ty * IY, z0 = tz * zc;
+    const int zend = min(z0 + zc, a.nz);  // step-2 planes [z0, zend)
+    const int tid = threadIdx.x;
+    // step-1 cells of this thread: halo-tile index e1[r], grid column (gx1, gy1)
+    int e1[R1], gx1[R1], gy1[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+        const int e = tid + r * T;
+        e1[r] = e;
+        const int lx = e % EX, ly = e / EX;
+        int gx = (x0 - 1 + lx) % a.nx, gy = (y0 - 1 + ly) % a.ny;
+        gx1[r] = gx < 0 ? gx + a.nx : gx;
+        gy1[r] = gy < 0 ? gy + a.ny : gy;
+    }
+    // step-2 cell of this thread
+    const int ix = tid % IX, iy = tid / IX;
+    const int e2 = (iy + 1) * EX + ix + 1;
+    const int gx2 = x0 + ix, gy2 = y0 + iy;
+    const bool act2 = tid < IX * IY && gx2 < a.nx && gy2 < a.ny;
+    const unsigned pn = (unsigned)a.nx * (unsigned)a.ny;
+    auto plane_of = [&](int p) {
+        int pz = p % a.nz;
+        return pz < 0 ? pz + a.nz : pz;
+    };
+    auto have1 = [&](int p) { return WALLS ? (p >= 0 && p < a.nz) : true; };
+    auto load1 = [&](int r, int pz, float fr[Q], float &D) {
+        pull3<float, WALLS>(a.fin, a.stride, a.nx, a.ny, a.nz, gx1[r], gy1[r], pz, fr);
+        D = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(a.coef) +
+                                             ((unsigned)pz * pn + (unsigned)gy1[r] * a.nx + gx1[r]) * 4u);
+    };
+
+    float fr[R1][Q];
+    float Dn[R1];
+    if (PF && have1(z0 - 1)) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r)
+            if (e1[r] < NE) load1(r, plane_of(z0 - 1), fr[r], Dn[r]);
+    }
+    for (int p = z0 - 1; p <= zend; ++p) {
+        const int rr = p - z0 + 1;  // >= 0
+        const int s2 = rr & 1, s3 = rr % 3;
+        // ---- step 1 on plane p
+        if (have1(p)) {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) {
+                if (e1[r] < NE) {
+                    if (!PF) load1(r, plane_of(p), fr[r], Dn[r]);
+                    double f[Q];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) f[q] = (double)fr[r][q];
+                    collide3(a, f, (double)Dn[r]);
+                    const int e = e1[r];
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) sin_[s2][i][e] = (float)f[kIn[i]];
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) sup[s3][i][e] = (float)f[kUp[i]];
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) sdn[s2][i][e] = (float)f[kDn[i]];
+                }
+            }
+        }
+        lds_barrier();
+        // ---- loads for the next plane's step 1, in flight during step 2
+        if (PF && p + 1 <= zend && have1(p + 1)) {
+#pragma unroll
+            for (int r = 0; r < R1; ++r)
+                if (e1[r] < NE) load1(r, plane_of(p + 1), fr[r], Dn[r]);
+        }
+        // ---- step 2 on plane p - 1
+        const int qz = p - 1;
+        if (qz >= z0 && qz < zend && act2) {
+            const int i0 = (rr - 1) & 1;       // plane qz: in-plane and -z slots
+            const int um = (rr + 1) % 3;       // plane qz - 1: +z slot
+            const int u0 = (rr + 2) % 3;       // plane qz: +z slot (top wall)
+            const int dp = rr & 1;             // plane qz + 1: -z slot
+            const bool blo = WALLS && qz == 0, bhi = WALLS && qz == a.nz - 1;
+            const int e = e2;
+            float g[Q];
+            g[0] = sin_[i0][0][e];
+            g[1] = sin_[i0][1][e - 1];
+            g[2] = sin_[i0][2][e + 1];
+            g[3] = sin_[i0][3][e - EX];
+            g[4] = sin_[i0][4][e + EX];
+            g[7] = sin_[i0][5][e - EX - 1];
+            g[8] = sin_[i0][6][e + EX + 1];
+            g[9] = sin_[i0][7][e + EX - 1];
+            g[10] = sin_[i0][8][e - EX + 1];
+            if (blo) {  // +z populations come back from the wall below as -z ones
+                g[5] = sdn[i0][0][e];
+                g[11] = sdn[i0][1][e];
+                g[14] = sdn[i0][2][e];
+                g[15] = sdn[i0][3][e];
+                g[18] = sdn[i0][4][e];
+            } else {
+                g[5] = sup[um][0][e];
+                g[11] = sup[um][1][e - 1];
+                g[14] = sup[um][2][e + 1];
+                g[15] = sup[um][3][e - EX];
+                g[18] = sup[um][4][e + EX];
+            }
+            if (bhi) {
+                g[6] = sup[u0][0][e];
+                g[12] = sup[u0][1][e];
+                g[13] = sup[u0][2][e];
+                g[16] = sup[u0][3][e];
+                g[17] = sup[u0][4][e];
+            } else {
+                g[6] = sdn[dp][0][e];
+                g[12] = sdn[dp][1][e + 1];
+                g[13] = sdn[dp][2][e - 1];
+                g[16] = sdn[dp][3][e + EX];
+                g[17] = sdn[dp][4][e - EX];
+            }
+            const unsigned c = (unsigned)qz * pn + (unsigned)gy2 * a.nx + gx2;
+            double f[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) f[q] = (double)g[q];
+            collide3(a, f, (double)*reinterpret_cast<const float *>(
+                               reinterpret_cast<const char *>(a.coef) + c * 4u));
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                *reinterpret_cast<float *>(reinterpret_cast<char *>(a.fout + (size_t)q * a.stride) + c * 4u) =
+                    (float)f[q];
+        }
+        // the next step 1 overwrites the slots of planes p - 1 (two-slot
+        // rings) and p - 2 (+z ring)
+        lds_barrier();
+    }
+}
+
 // Flow velocity and density of the current state (FP64), and per-block FP64
 // partial sums of u for the volume average.
 template <typename R, bool WALLS>
@@ -416,6 +613,7 @@ struct lbm3d_handle {
     double prev_u[3];
     bool have_prev;
     double *host_res;
+    int zchunk;         // planes per workgroup run of the two-step kernel
 };
 
 namespace lbm3 {
@@ -454,6 +652,45 @@ void launch_fields(const lbm3d_handle *h, double *u, double *rho, double *part)
 {
     hipLaunchKernelGGL((k3_fields<R, W>), dim3(h->L.ntiles), dim3(kBlock3), 0, h->stream, args_of<R>(h),
                        u, rho, part);
+}
+
+// Planes per workgroup run: the number of runs per column that minimises
+// (waves of workgroups over the CUs, one resident per CU) x (planes per run
+// + the two extra step-1 planes), so the grid neither leaves CUs idle in its
+// last wave nor repeats many halo planes.
+int zchunk_for(int nx, int ny, int nz)
+{
+    const int64_t cols = (int64_t)((nx + k2IX - 1) / k2IX) * ((ny + k2IY - 1) / k2IY);
+    const int64_t slots = std::max(1, lbm::device_cu_count());
+    int best_zc = nz;
+    int64_t best = -1;
+    for (int runs = 1; runs <= nz; ++runs) {
+        const int zc = (nz + runs - 1) / runs;
+        if (runs > 1 && (nz + zc - 1) / zc != runs) continue;  // same zc as a smaller count
+        const int64_t waves = (cols * runs + slots - 1) / slots;
+        const int64_t cost = waves * (zc + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_zc = zc;
+        }
+        if (zc <= 8) break;
+    }
+    return best_zc;
+}
+
+template <bool W>
+void launch_step2(const lbm3d_handle *h)
+{
+    const int zc = h->zchunk;
+    const int nt = ((h->p.nx + k2IX - 1) / k2IX) * ((h->p.ny + k2IY - 1) / k2IY) *
+                   ((h->p.nz + zc - 1) / zc);
+    hipLaunchKernelGGL((k3_step2<W>), dim3(nt), dim3(k2T), 0, h->stream, args_of<float>(h), zc);
+}
+
+// Two steps in one launch (FP32 state only).
+void step_twice(const lbm3d_handle *h)
+{
+    if (h->p.walls_z != 0) launch_step2<true>(h); else launch_step2<false>(h);
 }
 
 void step_once(const lbm3d_handle *h)
@@ -522,6 +759,7 @@ extern "C" lbm_status lbm3d_init(lbm3d_handle **out, const lbm3d_params *p, cons
     h->L = L;
     h->stream = stream;
     h->ws = static_cast<char *>(d_ws);
+    h->zchunk = zchunk_for(p->nx, p->ny, p->nz);
     if (hipHostMalloc((void **)&h->host_res, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete h;
         return set_error(LBM_EDEVICE, "lbm3d_init: hipHostMalloc failed");
@@ -566,10 +804,17 @@ extern "C" lbm_status lbm3d_step(lbm3d_handle *h, int64_t max_steps, double tol,
     bool last_checked = false;
     double u[3] = {0.0, 0.0, 0.0};
     while (done < max_steps) {
-        step_once(h);
+        // two steps per launch unless a check or the end falls in between
+        const int64_t to_check = check_every > 0 ? check_every - done % check_every : max_steps - done;
+        const int n = (h->p.pop_dtype == LBM_F32_SHIFTED &&
+                       std::min<int64_t>(to_check, max_steps - done) >= 2) ? 2 : 1;
+        if (n == 2)
+            step_twice(h);
+        else
+            step_once(h);
         h->cur ^= 1;
-        ++done;
-        ++h->steps_total;
+        done += n;
+        h->steps_total += n;
         last_checked = false;
         if (check_every > 0 && done % check_every == 0) {
             LBM_HIP(hipGetLastError());

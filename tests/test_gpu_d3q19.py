@@ -70,6 +70,29 @@ def test_steps_from_rest_match_oracle(L, shape, walls, dtype):
     s.close()
 
 
+@pytest.mark.parametrize("shape", [(70, 9, 70), (40, 17, 33), (5, 3, 1), (1, 1, 3), (33, 8, 2),
+                                   (64, 16, 32)])
+@pytest.mark.parametrize("walls", [0, 1])
+def test_two_step_launches_match_single_steps_bitwise(L, shape, walls):
+    """FP32 state: the two-steps-per-launch kernel (z-marching through a ring
+    of planes in LDS; chunks of 32 planes, halo tiles that wrap several times
+    on narrow grids) leaves exactly the state of single-step launches."""
+    nx, ny, nz = shape
+    kappa = I.lognormal_kappa3(nx, ny, nz, 1.0, 2.0, seed=8)
+    g = (1e-5, 3e-6, -2e-6)
+    a, _ = _solver(L, kappa, 0.7, g, walls, L.LBM_F32_SHIFTED)
+    b, _ = _solver(L, kappa, 0.7, g, walls, L.LBM_F32_SHIFTED)
+    a.step(10)                       # five two-step launches
+    for _ in range(10):
+        b.step(1)                    # ten single-step launches
+    fa, fb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+    assert np.array_equal(fa, fb)
+    assert np.abs(fa - D.rest_state(D.Params3(nx=nx, ny=ny, nz=nz, tau=0.7, eps=0.4, nu=0.1))
+                  .transpose(3, 0, 1, 2)).max() > 0
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("walls", [0, 1])
 @pytest.mark.parametrize("tau", [0.5, 0.53, 1.3])
 def test_random_state_one_step_f64(L, walls, tau):
@@ -139,15 +162,21 @@ class _Cells:
 
 def test_full_size_sampled_cells(L):
     """The D3Q19 workload at full size (256^3, sigma 1.5, walls in z) in the
-    launch configuration the benchmark times: after 12 steps from rest, one
-    more step on the GPU is checked at sampled cells (including the walls and
-    the periodic faces) against the oracle's step of the same state."""
+    launch configuration the benchmark times: 12 steps from rest in two-step
+    launches equal 12 single-step launches bitwise; then one more step on the
+    GPU is checked at sampled cells (including the walls and the periodic
+    faces) against the oracle's step of the same state."""
     w = I.workload_d3q19()
     kappa = w["kappa"]
     nz, ny, nx = kappa.shape
     s, p = _solver(L, kappa, w["tau"], w["g"], w["walls_z"], L.LBM_F32_SHIFTED, w["eps"], w["nu"])
-    s.step(12)
+    s.step(12)                                  # six two-step launches (runs of 128 planes)
     f_t = s.populations()                       # FP64 [19][nz][ny][nx] on the device
+    ref, _ = _solver(L, kappa, w["tau"], w["g"], w["walls_z"], L.LBM_F32_SHIFTED, w["eps"], w["nu"])
+    for _ in range(12):
+        ref.step(1)                             # single-step launches
+    assert torch.equal(ref.populations(), f_t)
+    ref.close()
     rng = np.random.default_rng(2)
     cells = np.stack([rng.integers(0, nx, 40), rng.integers(0, ny, 40), rng.integers(0, nz, 40)], 1)
     cells = np.concatenate([cells, [[0, 0, 0], [nx - 1, ny - 1, nz - 1], [5, 0, nz - 1],
