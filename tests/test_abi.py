@@ -123,6 +123,20 @@ def test_d3q19_params_validated_on_host():
         assert st == L.LBM_EINVAL and not h.value, field
 
 
+def test_size_limits_on_host():
+    """The largest grids each solver accepts: 9 (nx ny + 8192) < 2^31 for the
+    D2Q9 grid; (nx ny nz + 65536) x 4 B (FP32) or 8 B (FP64) below 4 GiB for
+    D3Q19 (32-bit byte offsets within a population plane)."""
+    assert L.lbm_workspace_bytes(L.make_params(16384, 14336, 0.8, 0.4, 0.1)) > 0
+    assert L.lbm_workspace_bytes(L.make_params(16384, 14592, 0.8, 0.4, 0.1)) == 0
+    assert L.lbm3d_workspace_bytes(L.make_params3(1024, 1024, 1023, 0.8, 0.4, 0.1)) > 0
+    assert L.lbm3d_workspace_bytes(L.make_params3(1024, 1024, 1024, 0.8, 0.4, 0.1)) == 0
+    f64 = L.make_params3(1024, 1024, 511, 0.8, 0.4, 0.1, pop_dtype=L.LBM_F64)
+    assert L.lbm3d_workspace_bytes(f64) > 0
+    f64.nz = 512
+    assert L.lbm3d_workspace_bytes(f64) == 0
+
+
 def test_cnn_forward_rejects_bad_n_sym_on_host():
     fake = ctypes.c_void_p(256 * 1024)
     for n_sym in (0, 9):

@@ -283,6 +283,52 @@ def test_fine_full_size_sampled(L):
     assert max(errs) < 1e-5, errs
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fine_near_maximum_size_sampled(L, dtype):
+    """A grid just under the size limit (9 (nx ny + 8192) < 2^31): 16384 x
+    14336 = 235M cells, walls in y, 12 steps (FP32: two six-step launches;
+    FP64: six two-step launches), checked at sampled cells, including the
+    last row and column, against the oracle on windows around them. The
+    permeability is a smooth closed-form pattern so the field is cheap to
+    build."""
+    nx, ny = 16384, 14336
+    assert 0.98 * 2 ** 31 < 9 * (nx * ny + 8192) < 2 ** 31
+    xs, ys = np.arange(nx), np.arange(ny)
+
+    def kap(yy, xx):
+        return np.exp(1.2 * np.sin(2 * np.pi * xx / 97.0)[None, :] *
+                      np.cos(2 * np.pi * yy / 131.0)[:, None])
+
+    k = kap(ys, xs)
+    g = (1e-6, 0.0)
+    pd = L.LBM_F32_SHIFTED if dtype == "f32" else L.LBM_F64
+    p = L.make_params(nx, ny, 0.8, 0.4, 0.1, 1.0, g[0], 0.0, 1, pd)
+    s = L.FineSolver(p, k)
+    del k
+    n = 12
+    st, done, _ = s.step(n)
+    assert st == L.LBM_OK and done == n
+    u, _ = s.fields()
+    samples = [(0, 0), (nx - 1, ny - 1), (nx - 1, 0), (0, ny - 1), (nx // 2, ny // 2),
+               (12345, 14000), (16000, 7)]
+    hw = n + 2
+    errs = []
+    for x0, y0 in samples:
+        wxs = np.arange(x0 - hw, x0 + hw + 1) % nx
+        ylo, yhi = max(0, y0 - hw), min(ny - 1, y0 + hw)
+        wys = np.arange(ylo, yhi + 1)
+        kw = np.ascontiguousarray(kap(wys, wxs))
+        po = O.Params(nx=len(wxs), ny=len(wys), tau=0.8, eps=0.4, nu=0.1, walls_y=1)
+        r = O.run(po, kw, g, max_steps=n)
+        _, ux, uy = O.moments(po, kw, r.f, g)
+        cx, cy = hw, y0 - ylo
+        ug = u[:, y0, x0].cpu().numpy()
+        scale = max(abs(ux[cy, cx]), 1e-30)
+        errs += [abs(ug[0] - ux[cy, cx]) / scale, abs(ug[1] - uy[cy, cx]) / scale]
+    s.close()
+    assert max(errs) < (1e-5 if dtype == "f32" else 1e-10), errs
+
+
 def test_fine_f32_error_over_full_step_count(L):
     """FP32 deviation storage over the 20000 steps of the fine workload, on a
     128 x 128 field of the same statistics (sigma 1.5, correlation 32 scaled
