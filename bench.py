@@ -44,6 +44,12 @@ DEPTH = 6          # time steps per launch of the fine-step kernel (FP32 state)
 STEP_KERNEL_SRC = os.path.join(ROOT, "paper_1312_0195_amd", "csrc", "lbm_fine.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fine_step_2048_hbm_counters.md")
 VALU_SUMMARY = os.path.join(ROOT, "profiles", "fine_step_2048_valu_counters.md")
+LOCAL_KERNEL_SRC = os.path.join(ROOT, "paper_1312_0195_amd", "csrc", "lbm_local.hip")
+LOCAL_VALU_SUMMARY = os.path.join(ROOT, "profiles", "local_keff_valu_counters.md")
+# one forward pass of the surrogate network per patch and symmetry: four 3x3
+# convolutions on 32 x 32 (1 -> 32, then 32 -> 32 channels) and the head MLP
+CNN_FLOPS_PER_PATCH = 2 * 1024 * 9 * (32 + 3 * 32 * 32) + 2 * (32 * 37 + 2 * 32)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def _src_hash(path):
@@ -51,7 +57,7 @@ def _src_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def _summary_value(path, pattern):
+def _summary_value(path, pattern, src=STEP_KERNEL_SRC):
     """A number from a committed counter summary, or None when the summary is
     missing or was taken on a different kernel source."""
     if not os.path.exists(path):
@@ -59,7 +65,7 @@ def _summary_value(path, pattern):
     txt = open(path).read()
     m_src = re.search(r"kernel source sha256\[:16\]:\s*([0-9a-f]{16})", txt)
     m_b = re.search(pattern, txt)
-    if not m_src or not m_b or m_src.group(1) != _src_hash(STEP_KERNEL_SRC):
+    if not m_src or not m_b or m_src.group(1) != _src_hash(src):
         return None
     return float(m_b.group(1))
 
@@ -147,7 +153,43 @@ def bench_local(L, torch, kappa_dev, reps=3):
                          lattice_updates=lu, mlups=lu / best / 1e6,
                          converged=int((r.flags == 0).sum()), items=int(r.flags.size),
                          mean_steps=float(r.steps.mean()))
-    return out
+        # on-chip bound: the VALU issue rate over the kernel's measured VALU
+        # lane instructions per lattice update (committed counter summary)
+        ipl = _summary_value(LOCAL_VALU_SUMMARY,
+                             name + r" VALU lane instructions per lattice update:\s*([0-9.]+)",
+                             LOCAL_KERNEL_SRC)
+        if ipl is not None:
+            bound = VALU_ISSUE_PER_S * 64 / ipl / 1e6
+            out[name].update(valu_lane_instructions_per_lu=ipl, onchip_valu_bound_mlups=round(bound),
+                             frac_of_onchip_bound=round(lu / best / 1e6 / bound, 4))
+        if name == "tiles32":
+            keff_tiles = r.keff.reshape(n // 32, n // 32, 4)
+    return out, keff_tiles
+
+
+def bench_coarse(L, torch, keff, r=32, reps=3):
+    """Time to steady state of the coarse grid built from the local K_eff of
+    the fine field's 32 x 32 tiles (64 x 64 coarse cells, tensor drag; Sec. 3
+    mapping of tau, nu, kappa and G): one persistent on-chip solve."""
+    ncy, ncx = keff.shape[:2]
+    fine = L.make_params(ncx * r, ncy * r, 0.8, 0.4, 0.1, 1.0, 1e-6, 0.0, 0)
+    kd = torch.as_tensor(np.ascontiguousarray(keff)).cuda()
+    u = torch.empty((2, ncy, ncx), dtype=torch.float64, device="cuda")
+    nb = L.lbm_coarse_workspace_bytes(ncx, ncy)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    best, steps = None, 0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, steps = L.lbm_coarse_solve(fine, r, kd, L.LBM_KEFF_TENSOR, None, 4_000_000, 1e-6, 100,
+                                       u, None, ws, nb)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert st == L.LBM_OK
+        best = dt if best is None else min(best, dt)
+    return dict(grid=f"{ncx}x{ncy} coarse cells (r {r}), tensor K_eff, rel. change 1e-6 per 100 steps",
+                steps=int(steps), seconds_to_steady_state=round(best, 5),
+                mlups=round(ncx * ncy * steps / best / 1e6, 1))
 
 
 def bench_surrogate(n_test=65536):
@@ -163,7 +205,12 @@ def bench_surrogate(n_test=65536):
     big, x0, y0, is_oor = T.test_set(n_test)
     r = T.evaluate(model, big, x0, y0, is_oor)
     e = r["keff_error_network_in_range"]
+    net_tflops = r["patches_per_s_network"] * r["n_sym"] * CNN_FLOPS_PER_PATCH / 1e12
     return dict(patches=r["n_patches"], flagged_to_lbm=r["flagged"],
+                network_roofline={"bound": "mfma", "achieved": round(net_tflops, 1),
+                                  "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": round(net_tflops / BF16_MFMA_PEAK_TFLOPS, 4),
+                                  "flops_per_patch_and_symmetry": CNN_FLOPS_PER_PATCH},
                 patches_per_s_network=r["patches_per_s_network"],
                 patches_per_s_network_plus_fallback=r["patches_per_s_network_plus_fallback"],
                 patches_per_s_lbm_only=r["patches_per_s_lbm_only"],
@@ -231,7 +278,17 @@ def bench_d3q19(L, torch, n=256, steps=200, warmup=20):
                     D3Q19_BYTES_PER_LU * cells / (us * 1e-6) / 1e9 / copy_gbs, 4))
 
 
-def cpu_baseline(kappa, steps):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(kappa, steps, single_steps=40):
     from oracle import oracle as O
     n = kappa.shape[0]
     p = O.Params(nx=n, ny=n, tau=0.8, eps=0.4, nu=0.1, walls_y=1)
@@ -240,9 +297,18 @@ def cpu_baseline(kappa, steps):
     O.run(p, kappa, (1e-6, 0.0), f=f, max_steps=steps)
     dt = time.perf_counter() - t0
     lu = steps * n * n
-    return dict(value=lu / dt / 1e6, unit="MLUPS", cores=O.num_threads(), kind="oracle",
+    threads = O.num_threads()
+    # the same oracle on one thread (its results do not depend on the count)
+    O.set_threads(1)
+    t1 = time.perf_counter()
+    O.run(p, kappa, (1e-6, 0.0), f=O.rest_state(p), max_steps=single_steps)
+    dt1 = time.perf_counter() - t1
+    O.set_threads(threads)
+    return dict(value=lu / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"{steps} steps of the {n}x{n} workload (FP64 C oracle, OpenMP over rows), "
-                       f"{dt:.1f} s")
+                       f"{dt:.1f} s",
+                single_thread_mlups=round(single_steps * n * n / dt1 / 1e6, 2),
+                single_thread_sample=f"{single_steps} steps, {dt1:.1f} s", cpu_model=_cpu_model())
 
 
 def main():
@@ -334,7 +400,8 @@ def main():
     result["step_forms"] = bench_forms(L, torch, kappa)
     if not args.no_local:
         kd = torch.as_tensor(kappa).cuda()
-        result["local_keff"] = bench_local(L, torch, kd)
+        result["local_keff"], keff_tiles = bench_local(L, torch, kd)
+        result["coarse"] = bench_coarse(L, torch, keff_tiles)
     if not args.no_surrogate and not args.no_local:
         result["keff_surrogate"] = bench_surrogate()
     if not args.no_d3q19:
