@@ -89,30 +89,45 @@ __device__ __forceinline__ int sym_src(int p, int sym)
 }
 
 // The four series/parallel features of k = exp(x) from the centred patch in
-// LDS: threads 0..31 take rows, 32..63 columns; fixed-order sums.
+// LDS, on all 512 threads: 8 threads per line (lines 0..31 rows, 32..63
+// columns) each sum 1/k and k over 4 pixels; fixed-order butterflies give
+// the line sums, then the sums over the 8 lines of each wave, then thread 0
+// adds the waves (rows: waves 0..3, columns: 4..7). lane_tmp: 16 floats.
 __device__ __forceinline__ void series_parallel(const float *xs, float *lane_tmp, float *feat)
 {
     const int tid = threadIdx.x;
-    if (tid < 64) {
-        const int r = tid & 31;
-        float hs = 0.0f, as = 0.0f;  // sums of 1/k and k along the line
-        for (int i = 0; i < kSide; ++i) {
-            const float x = tid < 32 ? xs[r * kSide + i] : xs[i * kSide + r];
-            hs += __expf(-x);
-            as += __expf(x);
-        }
-        lane_tmp[tid] = kSide / hs;        // harmonic mean of the line
-        lane_tmp[64 + tid] = as / kSide;   // arithmetic mean of the line
+    const int line = tid >> 3, part = tid & 7, r = line & 31;
+    float hs = 0.0f, as = 0.0f;  // sums of 1/k and k along the line
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = part * 4 + i;
+        const float x = line < 32 ? xs[r * kSide + j] : xs[j * kSide + r];
+        hs += __expf(-x);
+        as += __expf(x);
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        hs += __shfl_xor(hs, off, 64);
+        as += __shfl_xor(as, off, 64);
+    }
+    float h = kSide / hs;   // harmonic mean of the line
+    float ia = kSide / as;  // 1 / arithmetic mean of the line
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+        h += __shfl_xor(h, off, 64);
+        ia += __shfl_xor(ia, off, 64);
+    }
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) {
+        lane_tmp[wave] = h;
+        lane_tmp[8 + wave] = ia;
     }
     __syncthreads();
     if (tid == 0) {
-        float rh = 0.f, ch = 0.f, ria = 0.f, cia = 0.f;
-        for (int i = 0; i < 32; ++i) {
-            rh += lane_tmp[i];                  // rows: harmonic along x
-            ch += lane_tmp[32 + i];             // columns: harmonic along y
-            cia += 1.0f / lane_tmp[64 + 32 + i];  // columns: arithmetic along y
-            ria += 1.0f / lane_tmp[64 + i];       // rows: arithmetic along x
-        }
+        const float rh = (lane_tmp[0] + lane_tmp[1]) + (lane_tmp[2] + lane_tmp[3]);    // rows: harmonic along x
+        const float ch = (lane_tmp[4] + lane_tmp[5]) + (lane_tmp[6] + lane_tmp[7]);    // columns: harmonic along y
+        const float ria = (lane_tmp[8] + lane_tmp[9]) + (lane_tmp[10] + lane_tmp[11]);  // rows: 1/arithmetic
+        const float cia = (lane_tmp[12] + lane_tmp[13]) + (lane_tmp[14] + lane_tmp[15]);  // columns
         feat[0] = logf(rh / 32.0f);
         feat[1] = -logf(cia / 32.0f);
         feat[2] = logf(ch / 32.0f);
@@ -133,6 +148,77 @@ __device__ __forceinline__ float block_sum_fixed(float v, float *red)
     float t = 0.0f;
     for (int w = 0; w < kWaves; ++w) t += red[w];
     return t;
+}
+
+// Three fixed-order workgroup sums with one pair of barriers; red: 3 x kWaves.
+__device__ __forceinline__ void block_sum3_fixed(float &a, float &b, float &c, float *red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = a;
+        red[kWaves + (tid >> 6)] = b;
+        red[2 * kWaves + (tid >> 6)] = c;
+    }
+    __syncthreads();
+    float ta = 0.0f, tb = 0.0f, tc = 0.0f;
+    for (int w = 0; w < kWaves; ++w) {
+        ta += red[w];
+        tb += red[kWaves + w];
+        tc += red[2 * kWaves + w];
+    }
+    a = ta;
+    b = tb;
+    c = tc;
+}
+
+// conv1 (1 -> 32 channels) on MFMA: the nine taps are the K dimension (padded
+// to 32 with zeros), BF16 inputs and weights, FP32 accumulation, bias and
+// ReLU in FP32; output [pixel][channel] BF16 as the other layers.
+__device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 *__restrict__ out,
+                                           const float *__restrict__ prm, __bf16 *__restrict__ gout)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    bf16x8 w0, w1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int t = g * 8 + j;
+        w0[j] = (__bf16)(t < 9 ? prm[oW1 + t * kC + n] : 0.0f);
+        w1[j] = (__bf16)(t < 9 ? prm[oW1 + t * kC + 16 + n] : 0.0f);
+    }
+    const float b0 = prm[oB1 + n], b1 = prm[oB1 + 16 + n];
+    for (int tile = wave; tile < kPix / 16; tile += kWaves) {
+        const int y = tile >> 1, x0 = (tile & 1) * 16;
+        bf16x8 a;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int t = g * 8 + j;
+            const int tt = t < 9 ? t : 4;  // padded taps read any pixel and are zeroed
+            const float v = xs[wrap32(y + tap_dy(tt)) * kSide + wrap32(x0 + n + tap_dx(tt))];
+            a[j] = (__bf16)(t < 9 ? v : 0.0f);
+        }
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, z, 0, 0, 0);
+        const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, z, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = y * kSide + x0 + g * 4 + i;
+            const __bf16 v0 = (__bf16)fmaxf(acc0[i] + b0, 0.0f), v1 = (__bf16)fmaxf(acc1[i] + b1, 0.0f);
+            out[p * kC + n] = v0;
+            out[p * kC + 16 + n] = v1;
+            if (gout) {
+                gout[p * kC + n] = v0;
+                gout[p * kC + 16 + n] = v1;
+            }
+        }
+    }
 }
 
 // BF16 copies of conv2..4 weights:
@@ -163,60 +249,89 @@ struct FwdArgs {
 };
 
 // One 3x3, 32 -> 32 layer on MFMA. in/out are [pixel][channel] BF16 in LDS.
-// With POOL the ReLU outputs are summed per channel into pool_part[wave][32]
-// instead of being stored.
+// The product is D[co][pixel] = W[co][ci] X[ci][pixel] per tap (A: weights,
+// held in registers; B: 8 channels of one pixel per lane, one 16-byte LDS
+// read), so each lane ends with 4 consecutive output channels of one pixel
+// and stores them with one 8-byte write. Each wave takes two 16-pixel tiles
+// at a time: four independent accumulation chains per tap. With POOL the
+// ReLU outputs are summed per channel into pool_part[wave][32] instead of
+// being stored. Not inlined: inlined into k_forward, its ~200 live registers
+// (weights of the nine taps, prefetched operands) spilled to scratch; as a
+// call the layer has the register file to itself (measured 1.14 x faster).
 template <bool POOL>
-__device__ __forceinline__ void conv_mfma(const __bf16 *__restrict__ in, __bf16 *__restrict__ out,
-                                          const __bf16 *__restrict__ wfl, const float *__restrict__ bias,
-                                          __bf16 *__restrict__ gout, float *pool_part)
+__device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ in, __bf16 *__restrict__ out,
+                                                    const __bf16 *__restrict__ wfl,
+                                                    const float *__restrict__ bias,
+                                                    __bf16 *__restrict__ gout, float *pool_part)
 {
+    constexpr int U = 2;  // tiles per iteration
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = lane & 15, g = lane >> 4;  // n: output channel within tile; g: k-group / row group
+    const int n = lane & 15, g = lane >> 4;  // n: pixel within the tile (B, D) / co row (A); g: k-group
     bf16x8 w[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
             w[t][ct] = *reinterpret_cast<const bf16x8 *>(wfl + (t * kC + ct * 16 + n) * kC + g * 8);
-    const float b0 = bias[n], b1 = bias[16 + n];
-    float ps0 = 0.0f, ps1 = 0.0f;
-    for (int tile = wave; tile < kPix / 16; tile += kWaves) {
-        const int y = tile >> 1, x0 = (tile & 1) * 16;
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    float bb[2][4];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bb[ct][i] = bias[ct * 16 + g * 4 + i];
+    float ps[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    for (int tile = wave; tile < kPix / 16; tile += U * kWaves) {
+        int y[U], x0[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int tl = tile + u * kWaves;
+            y[u] = tl >> 1;
+            x0[u] = (tl & 1) * 16;
+        }
+        f32x4 acc[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) acc[u][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int p = wrap32(y + tap_dy(t)) * kSide + wrap32(x0 + n + tap_dx(t));
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(in + p * kC + g * 8);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[t][0], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w[t][1], acc1, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = wrap32(y[u] + tap_dy(t)) * kSide + wrap32(x0[u] + n + tap_dx(t));
+                const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(in + p * kC + g * 8);
+                acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][0], xb, acc[u][0], 0, 0, 0);
+                acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][1], xb, acc[u][1], 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int p = y * kSide + x0 + g * 4 + i;  // D row = pixel within the tile
-            const float v0 = fmaxf(acc0[i] + b0, 0.0f), v1 = fmaxf(acc1[i] + b1, 0.0f);
-            if (POOL) {
-                ps0 += v0;
-                ps1 += v1;
-            } else {
-                out[p * kC + n] = (__bf16)v0;
-                out[p * kC + 16 + n] = (__bf16)v1;
-            }
-            if (gout) {
-                gout[p * kC + n] = (__bf16)v0;
-                gout[p * kC + 16 + n] = (__bf16)v1;
+        for (int u = 0; u < U; ++u) {
+            const int p = y[u] * kSide + x0[u] + n;  // D column = pixel
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                bf16x4 v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float r = fmaxf(acc[u][ct][i] + bb[ct][i], 0.0f);
+                    if (POOL) ps[ct][i] += r;
+                    v[i] = (__bf16)r;
+                }
+                if (!POOL) *reinterpret_cast<bf16x4 *>(out + p * kC + ct * 16 + g * 4) = v;
+                if (gout) *reinterpret_cast<bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
             }
         }
     }
     if (POOL) {
-        // lanes n, n+16, n+32, n+48 hold the same channel: fixed-order sum
-        ps0 += __shfl_xor(ps0, 16, 64);
-        ps0 += __shfl_xor(ps0, 32, 64);
-        ps1 += __shfl_xor(ps1, 16, 64);
-        ps1 += __shfl_xor(ps1, 32, 64);
-        if (g == 0) {
-            pool_part[wave * kC + n] = ps0;
-            pool_part[wave * kC + 16 + n] = ps1;
-        }
+        // lanes n = 0..15 of a k-group hold the same 4 channels for different
+        // pixels: fixed-order butterfly over n
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = ps[ct][i];
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
+                if (n == 0) pool_part[wave * kC + ct * 16 + g * 4 + i] = v;
+            }
     }
 }
 
@@ -230,6 +345,7 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     float *red = pool_part + kWaves * kC;                      // [8]
     float *head = red + kWaves;                                // [37]
     float *tmp = head + kZ + 3;                                // [128]
+    float *red3 = tmp + 128;                                   // [3][8]
     const int tid = threadIdx.x;
     const float *prm = a.prm;
 
@@ -250,9 +366,11 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
                 const int p0 = tid, p1 = tid + kT;
                 const float rx = x0 * xs[(p0 & ~31) | wrap32(p0 + 1)] + x1 * xs[(p1 & ~31) | wrap32(p1 + 1)];
                 const float ry = x0 * xs[(p0 + kSide) & (kPix - 1)] + x1 * xs[(p1 + kSide) & (kPix - 1)];
-                const float var = block_sum_fixed(x0 * x0 + x1 * x1, red) * (1.0f / kPix);
-                const float cx = block_sum_fixed(rx, red) * (1.0f / kPix);
-                const float cy = block_sum_fixed(ry, red) * (1.0f / kPix);
+                float var = x0 * x0 + x1 * x1, cx = rx, cy = ry;
+                block_sum3_fixed(var, cx, cy, red3);
+                var *= 1.0f / kPix;
+                cx *= 1.0f / kPix;
+                cy *= 1.0f / kPix;
                 if (tid == 0) {
                     float *st = a.stats + 8 * (size_t)b;
                     st[0] = m;
@@ -263,27 +381,9 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
             }
             series_parallel(xs, tmp, head + kC + 1);
             if (a.stats && t == 0 && tid < 4) a.stats[8 * (size_t)b + 4 + tid] = head[kC + 1 + tid];
-            // ---- conv1: 1 -> 32 channels, FP32 on the VALU ----
+            // ---- conv1: 1 -> 32 channels on MFMA ----
             __bf16 *g1 = a.acts ? a.acts + ((size_t)0 * a.batch + b) * kPix * kC : nullptr;
-            for (int p = tid; p < kPix; p += kT) {
-                const int y = p >> 5, x = p & 31;
-                float nb[9];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) nb[q] = xs[wrap32(y + tap_dy(q)) * kSide + wrap32(x + tap_dx(q))];
-#pragma unroll
-                for (int co = 0; co < kC; co += 8) {
-                    bf16x8 v;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        float z = prm[oB1 + co + j];
-#pragma unroll
-                        for (int q = 0; q < 9; ++q) z += nb[q] * prm[oW1 + q * kC + co + j];
-                        v[j] = (__bf16)fmaxf(z, 0.0f);
-                    }
-                    *reinterpret_cast<bf16x8 *>(bufA + p * kC + co) = v;
-                    if (g1) *reinterpret_cast<bf16x8 *>(g1 + p * kC + co) = v;
-                }
-            }
+            conv1_mfma(xs, bufA, prm, g1);
             __syncthreads();
             // ---- conv2..conv4 on MFMA ----
             __bf16 *g2 = a.acts ? a.acts + ((size_t)1 * a.batch + b) * kPix * kC : nullptr;
@@ -303,26 +403,39 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
             }
             if (tid == 0) head[kC] = m;
             __syncthreads();
-            if (tid < 64) {
-                float hval = 0.0f;
-                if (tid < kH) {
-                    float z = prm[oC1 + tid];
-                    for (int k = 0; k < kZ; ++k) z += prm[oM1 + tid * kZ + k] * head[k];
-                    hval = fmaxf(z, 0.0f);
-                }
-                float y0 = tid < kH ? prm[oM2 + tid] * hval : 0.0f;
-                float y1 = tid < kH ? prm[oM2 + kH + tid] * hval : 0.0f;
+            {
+                // hidden unit h on 16 threads, each summing inputs k = j, j + 16, j + 32
+                const int h = tid >> 4, j = tid & 15;
+                float zh = 0.0f;
+                for (int k = j; k < kZ; k += 16) zh += prm[oM1 + h * kZ + k] * head[k];
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
+                for (int off = 1; off < 16; off <<= 1) zh += __shfl_xor(zh, off, 64);
+                const float hval = fmaxf(zh + prm[oC1 + h], 0.0f);
+                float y0 = j == 0 ? prm[oM2 + h] * hval : 0.0f;
+                float y1 = j == 0 ? prm[oM2 + kH + h] * hval : 0.0f;
+#pragma unroll
+                for (int off = 16; off < 64; off <<= 1) {
                     y0 += __shfl_xor(y0, off, 64);
                     y1 += __shfl_xor(y1, off, 64);
                 }
-                y0 += prm[oC2] + m;
-                y1 += prm[oC2 + 1] + m;
-                // a transposed patch predicts (kyy, kxx) of the original
-                acc0 += (sym & 1) ? y1 : y0;
-                acc1 += (sym & 1) ? y0 : y1;
+                if ((tid & 63) == 0) {
+                    red3[tid >> 6] = y0;
+                    red3[kWaves + (tid >> 6)] = y1;
+                }
                 if (a.pool_out && tid < kZ) a.pool_out[(size_t)b * kZ + tid] = head[tid];
+                __syncthreads();
+                if (tid == 0) {
+                    float s0 = 0.0f, s1 = 0.0f;
+                    for (int w = 0; w < kWaves; ++w) {
+                        s0 += red3[w];
+                        s1 += red3[kWaves + w];
+                    }
+                    s0 += prm[oC2] + m;
+                    s1 += prm[oC2 + 1] + m;
+                    // a transposed patch predicts (kyy, kxx) of the original
+                    acc0 += (sym & 1) ? s1 : s0;
+                    acc1 += (sym & 1) ? s0 : s1;
+                }
             }
             __syncthreads();
         }
@@ -340,6 +453,7 @@ __global__ __launch_bounds__(kT) void k_stats(const float *__restrict__ logk, in
 {
     __shared__ float xs[kPix];
     __shared__ float red[kWaves];
+    __shared__ float red3[3 * kWaves];
     __shared__ float tmp[128];
     __shared__ float feat[4];
     const int tid = threadIdx.x;
@@ -354,9 +468,11 @@ __global__ __launch_bounds__(kT) void k_stats(const float *__restrict__ logk, in
         const int p0 = tid, p1 = tid + kT;
         const float rx = x0 * xs[(p0 & ~31) | wrap32(p0 + 1)] + x1 * xs[(p1 & ~31) | wrap32(p1 + 1)];
         const float ry = x0 * xs[(p0 + kSide) & (kPix - 1)] + x1 * xs[(p1 + kSide) & (kPix - 1)];
-        const float var = block_sum_fixed(x0 * x0 + x1 * x1, red) * (1.0f / kPix);
-        const float cx = block_sum_fixed(rx, red) * (1.0f / kPix);
-        const float cy = block_sum_fixed(ry, red) * (1.0f / kPix);
+        float var = x0 * x0 + x1 * x1, cx = rx, cy = ry;
+        block_sum3_fixed(var, cx, cy, red3);
+        var *= 1.0f / kPix;
+        cx *= 1.0f / kPix;
+        cy *= 1.0f / kPix;
         series_parallel(xs, tmp, feat);
         if (tid == 0) {
             float *st = stats + 8 * (size_t)b;
@@ -670,7 +786,7 @@ SurLayout sur_layout(int batch, bool train)
     return L;
 }
 
-constexpr size_t kFwdLds = 2 * kPix * kC * 2 + (kPix + kWaves * kC + kWaves + kZ + 3 + 128) * 4;
+constexpr size_t kFwdLds = 2 * kPix * kC * 2 + (kPix + kWaves * kC + kWaves + kZ + 3 + 128 + 3 * kWaves) * 4;
 constexpr size_t kBwdLds = 2 * kPix * kC * 2 + (kPix + kWaves + kC) * 4;
 
 lbm_status check_ws(void *d_ws, size_t ws_bytes, size_t need, const char *fn)
