@@ -257,9 +257,10 @@ lbm_status lbm_block_average(const double *d_in, int32_t nx, int32_t ny, int32_t
  * Parameters: one FP32 vector, in this order:
  *   W1[9][32], b1[32], then for l = 2, 3, 4: Wl[9][32 ci][32 co], bl[32],
  *   M1[32][37], c1[32], M2[2][32], c2[2]          (lbm_cnn_param_count() floats)
- * conv2..4 run on BF16 MFMA with FP32 accumulation; conv1, the features, the
- * head, the loss and Adam are FP32. Inputs: d_logk FP32 [batch][32][32]
- * (x fastest).
+ * The four convolutions run on BF16 MFMA with FP32 accumulation (conv1 with
+ * its nine taps as the K dimension, the input and W1 rounded to BF16); the
+ * features, the head, the loss, the conv1 gradients and Adam are FP32.
+ * Inputs: d_logk FP32 [batch][32][32] (x fastest).
  * Symmetries: K_eff transforms with the eight symmetries of the square. A
  * symmetry code sym = t + 2 fx + 4 fy (0..7) means: output pixel (y, x) of the
  * transformed patch reads input pixel (v, u), where (u, v) = (x, y), exchanged
