@@ -276,3 +276,25 @@ def test_pipelined_fallback_matches_separate_paths(L):
     y_lbm, _ = S.label_patches(None, x0[~ok], y0[~ok], kappa_dev=kd)
     assert np.allclose(out[~ok], y_lbm, rtol=0, atol=1e-12)
     assert secs > 0
+
+
+def test_trained_network_gains_over_the_method_without_it(L):
+    """What the trained network (the committed model) adds, on 16384 fresh
+    test patches (90% from in-range fields, 10% from three out-of-range
+    kinds), with the batched local LBM as the reference: (1) against the
+    method without the local problems (the block geometric mean of kappa as
+    K_eff) it is far more accurate; (2) against the method without the
+    network (the batched LBM for every patch) the network plus LBM fallback
+    is faster, at the accuracy the surrogate path is specified for (2%)."""
+    from paper_1312_0195_amd import surrogate as S
+    from paper_1312_0195_amd import train_surrogate as T
+    model = S.Surrogate.load(T.DEFAULT_MODEL)
+    big, x0, y0, kind = T.test_set(16384)
+    r = T.evaluate(model, big, x0, y0, kind, sweep_nsym=(model.n_sym,))
+    net, geo = r["keff_error_network_in_range"], r["keff_error_geometric_mean_in_range"]
+    assert r["lbm_label_failures"] == 0
+    assert net["p50"] < 0.01 and net["p95"] < 0.025, net
+    assert net["p50"] < geo["p50"] / 10 and net["p95"] < geo["p95"] / 10, (net, geo)
+    assert r["keff_error_combined_all"]["p95"] < 0.05, r["keff_error_combined_all"]
+    speedup = r["patches_per_s_network_plus_fallback"] / r["patches_per_s_lbm_only"]
+    assert speedup > 1.5, (speedup, r["patches_per_s_network_plus_fallback"], r["patches_per_s_lbm_only"])
