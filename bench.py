@@ -134,6 +134,38 @@ def bench_forms(L, torch, kappa, steps=2000):
     return out
 
 
+def bench_paper_sec41(L, torch):
+    """The paper's only timing (Sec. 4.1): 100 x 100 periodic, tau 0.53, the
+    block field of Eq. kappa-forcemodel, 200 000 steps, Guo form about 23 min
+    and Shan-Chen form about 21 min on the paper's (unstated) CPU. Here: both
+    forms with FP64 populations (the paper's precision is not stated; its
+    7-digit K_eff values imply FP64) and the Shan-Chen form with FP32
+    deviations, each the full 200 000 steps on one MI355X."""
+    from paper_1312_0195_amd import inputs as I
+    w = I.workload_sec41()
+    stream = torch.cuda.current_stream()
+    out = {"workload": "Sec. 4.1: 100x100 periodic, tau 0.53, eps 0.8, block field, 200000 steps",
+           "paper_minutes": {"shan_chen": 21, "guo": 23, "hardware": "not stated (CPU)"}}
+    for name, scheme, dtype in (("shan_chen_f64", L.LBM_SCHEME_SHAN_CHEN, L.LBM_F64),
+                                ("guo_f64", L.LBM_SCHEME_GUO, L.LBM_F64),
+                                ("shan_chen_f32", L.LBM_SCHEME_SHAN_CHEN, L.LBM_F32_SHIFTED)):
+        p = L.make_params(w["nx"], w["ny"], w["tau"], w["eps"], w["nu"], 1.0, w["g"][0], w["g"][1],
+                          0, dtype, L.LBM_PERM_SCALAR, scheme)
+        s = L.FineSolver(p, w["kappa"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st, done, _ = s.step(w["steps"], 0.0, 0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert st == L.LBM_OK and done == w["steps"]
+        sec = e0.elapsed_time(e1) * 1e-3
+        out[name + "_seconds"] = round(sec, 3)
+        s.close()
+    out["speedup_vs_paper_shan_chen_f64"] = round(21 * 60 / out["shan_chen_f64_seconds"], 1)
+    return out
+
+
 def bench_local(L, torch, kappa_dev, reps=3):
     from paper_1312_0195_amd import inputs as I
     n = kappa_dev.shape[0]
@@ -398,6 +430,7 @@ def main():
         "wall_s": round(fine["wall_s"], 3),
     }
     result["step_forms"] = bench_forms(L, torch, kappa)
+    result["paper_sec41_timing"] = bench_paper_sec41(L, torch)
     if not args.no_local:
         kd = torch.as_tensor(kappa).cuda()
         result["local_keff"], keff_tiles = bench_local(L, torch, kd)

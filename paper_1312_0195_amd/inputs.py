@@ -289,6 +289,17 @@ def workload_upscale(seed: int = 1, n: int = 4096, channels: bool = False) -> di
     return dict(nx=n, ny=n, kappa=k, walls_y=0, **COMMON)
 
 
+def workload_sec41() -> dict:
+    """Sec. 4.1 (the comparison of the two force forms, the paper's only
+    timing): 100 x 100 periodic, dx 0.01 m, dt 1e-4 s, tau 0.53, nu 2e-6
+    m^2/s, eps 0.8, G = (2, 0) m/s^2, the block field of Eq.
+    kappa-forcemodel; 200 000 steps. Lattice units."""
+    U = LatticeUnits(0.01, 1e-4)
+    return dict(nx=100, ny=100, kappa=np.ascontiguousarray(U.kappa(block_field(100))),
+                tau=0.53, eps=0.8, nu=float(U.nu(2e-6)), g=(float(U.force(2.0)), 0.0),
+                steps=200_000, units=U)
+
+
 def workload_d3q19(seed: int = 1, n: int = 256) -> dict:
     """D3Q19 fine grid: n^3 (256^3 by default), sigma 1.5, correlation length
     16 n / 256, walls in z (x and y periodic), the same physics as the
