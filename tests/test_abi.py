@@ -137,6 +137,24 @@ def test_size_limits_on_host():
     assert L.lbm3d_workspace_bytes(f64) == 0
 
 
+def test_empty_and_degenerate_inputs_on_host():
+    """Empty batches: zero local problems is a no-op (no pointer is read);
+    an empty CNN batch, a block size that does not divide the grid and a
+    zero-sized workspace request are rejected before any device work."""
+    lp = L.lbm_local_params(0.8, 0.4, 0.1, 1e-6, 1e-6, 100, 1000, L.LBM_F32_SHIFTED, 0)
+    st = L.lib().lbm_local_keff(ctypes.byref(lp), 0, None, None, None, None, None, 1, 1, None,
+                                None, None, None, 0, 0, None, 0, None)
+    assert st == L.LBM_OK
+    fake = ctypes.c_void_p(256 * 1024)
+    assert L.lib().lbm_cnn_forward(fake, 0, fake, 1, fake, None, fake, 1 << 20, None) == L.LBM_EINVAL
+    assert L.lib().lbm_patch_stats(0, fake, fake, None) == L.LBM_EINVAL
+    assert L.lbm_cnn_workspace_bytes(0, 0) == 0
+    assert L.lib().lbm_block_average(fake, 10, 10, 1, 3, fake, None) == L.LBM_EINVAL
+    assert L.lib().lbm_block_average(fake, 0, 10, 1, 1, fake, None) == L.LBM_EINVAL
+    assert L.lbm_workspace_bytes(L.make_params(0, 8, 0.8, 0.4, 0.1)) == 0
+    assert L.lbm_local_workspace_bytes(0) >= 0
+
+
 def test_cnn_forward_rejects_bad_n_sym_on_host():
     fake = ctypes.c_void_p(256 * 1024)
     for n_sym in (0, 9):
