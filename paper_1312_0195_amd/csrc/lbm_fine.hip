@@ -360,7 +360,15 @@ template <> struct TileD<float, 4> : TileShape<LBM_TILE4> {};
 template <> struct TileD<float, LBM_DEEP> : TileShape<LBM_TILE6> {};
 constexpr int kDeep = LBM_DEEP;
 static_assert(kDeep > 4, "the deepest kernel must take more than 4 steps");
+#ifndef LBM_TILE6D
+#define LBM_TILE6D 32, 12, 256
+#endif
+#ifndef LBM_TILE4D
+#define LBM_TILE4D 32, 16, 256
+#endif
 template <> struct TileD<double, 2> : TileShape<32, 16, 256> {};
+template <> struct TileD<double, 4> : TileShape<LBM_TILE4D> {};
+template <> struct TileD<double, LBM_DEEP> : TileShape<LBM_TILE6D> {};
 
 // D time steps per launch (temporal blocking). Phase 1 takes step t on the
 // workgroup's tile plus a (D - 1)-cell halo, pulling from HBM and keeping the
@@ -898,10 +906,8 @@ struct StepDFn {
     }
     static void run(const lbm_handle *h, int depth)
     {
-        if constexpr (std::is_same<R, float>::value) {
-            if (depth == kDeep) return launch<kDeep>(h);
-            if (depth == 4) return launch<4>(h);
-        }
+        if (depth == kDeep) return launch<kDeep>(h);
+        if (depth == 4) return launch<4>(h);
         launch<2>(h);
     }
 };
@@ -910,9 +916,9 @@ struct StepDFn {
 // check (or the end); 1 runs the single-step kernel.
 int launch_depth(const lbm_handle *h, int64_t room)
 {
-    const bool f64 = h->p.pop_dtype == LBM_F64;
-    if (!f64 && room >= kDeep) return kDeep;
-    if (!f64 && room >= 4) return 4;
+    (void)h;
+    if (room >= kDeep) return kDeep;
+    if (room >= 4) return 4;
     return room >= 2 ? 2 : 1;
 }
 template <typename R, bool W, int PK, bool FF>

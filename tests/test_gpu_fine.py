@@ -153,9 +153,9 @@ def test_fine_converges_to_oracle_steady_state(L):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_multi_step_launches_match_single_steps_bitwise(L, nx, ny, walls, dtype):
     """lbm_step advances several steps per launch (temporal blocking in LDS:
-    6, 4 or 2 steps with FP32 state, 2 with FP64) whenever no check falls in
-    between; the state must equal that of single-step launches bit for bit
-    (ragged tiles, walls, periodic y, grids smaller than the halo)."""
+    6, 4 or 2 steps, FP32 or FP64 state) whenever no check falls in between;
+    the state must equal that of single-step launches bit for bit (ragged
+    tiles, walls, periodic y, grids smaller than the halo)."""
     dt = L.LBM_F64 if dtype == "f64" else L.LBM_F32_SHIFTED
     k = I.lognormal_kappa(nx, ny, 1.5, 6.0, seed=11)
     p = L.make_params(nx, ny, 0.7, 0.4, 0.1, 1.0, 1e-6, 3e-7, walls, dt)
