@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-local", action="store_true")
     ap.add_argument("--no-d3q19", action="store_true")
+    ap.add_argument("--no-paper-timing", action="store_true",
+                    help="skip the 100 x 100 Sec. 4.1 leg (its 200000 steps swamp a profile)")
     ap.add_argument("--only-d3q19", action="store_true",
                     help="run the D3Q19 leg alone (for profiling) and print its object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -430,7 +432,8 @@ def main():
         "wall_s": round(fine["wall_s"], 3),
     }
     result["step_forms"] = bench_forms(L, torch, kappa)
-    result["paper_sec41_timing"] = bench_paper_sec41(L, torch)
+    if not args.no_paper_timing:
+        result["paper_sec41_timing"] = bench_paper_sec41(L, torch)
     if not args.no_local:
         kd = torch.as_tensor(kappa).cuda()
         result["local_keff"], keff_tiles = bench_local(L, torch, kd)
