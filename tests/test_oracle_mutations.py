@@ -7,8 +7,10 @@ import pytest
 from oracle import d3q19 as D
 from oracle import direct as DS
 
+import test_cnn_oracle as PC
 import test_oracle_d3q19 as P3
 import test_oracle_pins as P2
+from oracle import cnn_oracle as CO
 
 
 def _fails(fn, *args):
@@ -88,3 +90,71 @@ def test_window_off_by_one_fails_window_pins(monkeypatch, lo, hi):
         except AssertionError:
             failed += 1
     assert failed >= 1
+
+
+def _any_fails(fns):
+    failed = 0
+    for fn in fns:
+        try:
+            fn()
+        except AssertionError:
+            failed += 1
+    return failed
+
+
+def test_cnn_shift_reversed_fails_conv_pin(monkeypatch):
+    monkeypatch.setattr(CO, "_shift", lambda a, dy, dx: np.roll(a, shift=(dy, dx), axis=(1, 2)))
+    _fails(PC.test_conv_matches_brute_force_loops)
+
+
+def test_cnn_backward_slips_fail_gradient_pin(monkeypatch):
+    good_bwd = CO.conv3x3_backward
+
+    def bwd_wrong_way(a, W, g):
+        da = np.zeros_like(a)
+        dW = np.zeros_like(W)
+        for t, (dy, dx) in enumerate(CO.TAPS):
+            dW[t] = np.einsum("bhwi,bhwo->io", CO._shift(a, dy, dx), g)
+            da += CO._shift(g @ W[t].T, dy, dx)          # sent back the wrong way
+        return da, dW, g.sum(axis=(0, 1, 2))
+
+    monkeypatch.setattr(CO, "conv3x3_backward", bwd_wrong_way)
+    _fails(PC.test_gradients_match_central_differences)
+    monkeypatch.setattr(CO, "conv3x3_backward", good_bwd)
+    PC.test_gradients_match_central_differences()         # the unpatched oracle passes
+
+
+def test_cnn_transpose_first_fails_transform_pin(monkeypatch):
+    def transform(logk, sym):
+        t, fx, fy = sym & 1, (sym >> 1) & 1, (sym >> 2) & 1
+        a = np.asarray(logk)
+        if t:
+            a = np.swapaxes(a, 1, 2)                      # transpose before the mirrors
+        if fx:
+            a = a[:, :, ::-1]
+        if fy:
+            a = a[:, ::-1, :]
+        return np.ascontiguousarray(a)
+
+    monkeypatch.setattr(CO, "transform", transform)
+    assert _any_fails([PC.test_transform_matches_pixel_loops_and_forms_the_group,
+                       PC.test_symmetric_prediction_is_equivariant]) >= 1
+
+
+def test_cnn_adam_without_bias_correction_fails_pin(monkeypatch):
+    def adam_step(p, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        for k in p:
+            m = state.setdefault("m_" + k, np.zeros_like(p[k]))
+            v = state.setdefault("v_" + k, np.zeros_like(p[k]))
+            m[...] = b1 * m + (1 - b1) * g[k]
+            v[...] = b2 * v + (1 - b2) * g[k] ** 2
+            p[k] = p[k] - lr * m / (np.sqrt(v) + eps)
+
+    monkeypatch.setattr(CO, "adam_step", adam_step)
+    _fails(PC.test_adam_first_step_is_signed_learning_rate)
+
+
+def test_cnn_series_parallel_axes_swapped_fails_pin(monkeypatch):
+    good = CO.series_parallel
+    monkeypatch.setattr(CO, "series_parallel", lambda x: good(np.swapaxes(x, 1, 2)))
+    _fails(PC.test_series_parallel_features_of_layered_patch)
