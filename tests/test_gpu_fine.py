@@ -171,7 +171,8 @@ def test_multi_step_launches_match_single_steps_bitwise(L, nx, ny, walls, dtype)
 
 
 @pytest.mark.parametrize("scheme,perm_kind,force", [(0, 4, True), (1, 1, True), (0, 1, True)])
-def test_multi_step_launches_bitwise_all_kernel_forms(L, scheme, perm_kind, force):
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_multi_step_launches_bitwise_all_kernel_forms(L, scheme, perm_kind, force, dtype):
     """The same on the other kernel forms: tensor permeability, the Guo form,
     a per-cell force field (periodic y, ragged tiles)."""
     nx, ny = 150, 45
@@ -184,7 +185,8 @@ def test_multi_step_launches_bitwise_all_kernel_forms(L, scheme, perm_kind, forc
     else:
         k = I.lognormal_kappa(nx, ny, 1.5, 6.0, seed=12)
     f = 1e-6 * rng.standard_normal((ny, nx, 2)) if force else None
-    p = L.make_params(nx, ny, 0.9, 0.4, 0.1, 1.0, 1e-6, 0.0, 0, L.LBM_F32_SHIFTED, perm_kind, scheme)
+    dt = L.LBM_F64 if dtype == "f64" else L.LBM_F32_SHIFTED
+    p = L.make_params(nx, ny, 0.9, 0.4, 0.1, 1.0, 1e-6, 0.0, 0, dt, perm_kind, scheme)
     a = L.FineSolver(p, k, f)
     b = L.FineSolver(p, k, f)
     a.step(24)                 # 6 x 4 steps per launch
