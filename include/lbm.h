@@ -159,7 +159,22 @@ typedef struct {
                              Eq. tensor-kappa, is taken over the inner window
                              [m, side - m)^2 only; 0 = the whole patch. Every
                              side must exceed 2 m. */
+    int32_t schedule;     /* order in which the items of one side start:
+                             LBM_SCHEDULE_GIVEN or LBM_SCHEDULE_COST. Results
+                             do not depend on it, only the run time. */
 } lbm_local_params;
+
+/* Start order of the local problems. An item's step count varies by orders
+ * of magnitude between patches (the mean flow relaxes on the time scale
+ * kappa / (eps nu) of the drag term), so a batch ends when its slowest items
+ * end. LBM_SCHEDULE_COST starts the items of each side in descending order of
+ * the patch's arithmetic-mean permeability (a device pre-pass over the
+ * patches, binned at four bins per octave; ties in any order), so the long
+ * items start first and the short ones fill in behind them. */
+enum {
+    LBM_SCHEDULE_GIVEN = 0, /* the order of the patch arrays (within a side) */
+    LBM_SCHEDULE_COST = 1   /* longest predicted first */
+};
 
 /* One row of the tile table: how items of side `side` are laid out on a
  * workgroup of block_threads threads. slot_threads threads share one item

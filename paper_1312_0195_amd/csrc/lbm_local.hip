@@ -354,7 +354,7 @@ __global__ void k_local_prefill(int n, const int *__restrict__ mask, double *__r
                                 int *__restrict__ counters, int ncounters)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ncounters) counters[i] = 0;
+    if (i < ncounters) counters[i] = 0;  // item counters and the schedule histogram
     if (i >= n) return;
     const double qnan = __longlong_as_double(0x7ff8000000000000LL);
     for (int d = 0; d < 2; ++d) {
@@ -367,18 +367,97 @@ __global__ void k_local_prefill(int n, const int *__restrict__ mask, double *__r
     }
 }
 
+// ---- start order (LBM_SCHEDULE_COST) --------------------------------------
+// Key of an item: its side class in the high part (classes keep their
+// ranges), then the bin of the patch's arithmetic-mean permeability, largest
+// first: kCostBins bins of a quarter octave each, from 2^-8 up.
+constexpr int kCostBins = 64;
+
+__global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ items,
+                                                    const ClassDesc *__restrict__ classes, int nclasses,
+                                                    const double *__restrict__ field, int fnx, int fny,
+                                                    int *__restrict__ keys, int *__restrict__ hist)
+{
+    __shared__ double red[4];
+    const int item = blockIdx.x;
+    const int4 it = items[item];
+    const int S = it.z, n = S * S;
+    double sum = 0.0;
+    for (int c = threadIdx.x; c < n; c += 256) {
+        const int fx = (it.x + c % S) % fnx, fy = (it.y + c / S) % fny;
+        sum += field[(size_t)fy * fnx + fx];
+    }
+    sum = wave_sum(sum);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double mean = ((red[0] + red[1]) + (red[2] + red[3])) / (double)n;
+    int bin;
+    if (mean > 0.0 && isfinite(mean))
+        bin = min(kCostBins - 1, max(0, (int)floor(4.0 * log2(mean)) + kCostBins / 2));
+    else
+        bin = (mean > 0.0) ? kCostBins - 1 : 0;  // +inf: no drag, slowest; NaN or <= 0: ends at once
+    int cls = 0;
+    for (int c = 0; c < nclasses; ++c)
+        if (item >= classes[c].begin && item < classes[c].begin + classes[c].count) cls = c;
+    const int key = cls * kCostBins + (kCostBins - 1 - bin);
+    keys[item] = key;
+    atomicAdd(&hist[key], 1);
+}
+
+// Exclusive scan of the key histogram (one workgroup of 256 threads): the
+// first position of each key in the ordered item list.
+__global__ __launch_bounds__(256) void k_local_scan(const int *__restrict__ hist, int *__restrict__ cursor,
+                                                    int nh)
+{
+    __shared__ int part[256];
+    const int t = threadIdx.x;
+    const int chunk = (nh + 255) / 256, lo = min(t * chunk, nh), hi = min(lo + chunk, nh);
+    int own = 0;
+    for (int i = lo; i < hi; ++i) own += hist[i];
+    part[t] = own;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int pos = part[t] - own;
+    for (int i = lo; i < hi; ++i) {
+        cursor[i] = pos;
+        pos += hist[i];
+    }
+}
+
+__global__ void k_local_scatter(int n, const int4 *__restrict__ items, const int *__restrict__ keys,
+                                int *__restrict__ cursor, int4 *__restrict__ sorted)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    sorted[atomicAdd(&cursor[keys[i]], 1)] = items[i];
+}
+
 struct LocalLayout {
-    size_t off_items, off_classes, off_counters, off_mask, total;
+    size_t off_items, off_classes, off_counters, off_mask, off_sorted, off_keys, total;
 };
+
+// counters: kMaxClasses item counters, then the schedule histogram and its
+// cursors (kMaxClasses x kCostBins each)
+constexpr int kHist = kMaxClasses * kCostBins;
+constexpr int kNumCounters = kMaxClasses + 2 * kHist;
 
 LocalLayout local_layout(int n_patches)
 {
     LocalLayout L{};
     size_t off = 0;
-    L.off_items = off;    off = align_up(off + sizeof(int4) * 2 * (size_t)std::max(n_patches, 1));
+    const size_t items = 2 * (size_t)std::max(n_patches, 1);
+    L.off_items = off;    off = align_up(off + sizeof(int4) * items);
     L.off_classes = off;  off = align_up(off + sizeof(ClassDesc) * kMaxClasses);
-    L.off_counters = off; off = align_up(off + sizeof(int) * kMaxClasses);
+    L.off_counters = off; off = align_up(off + sizeof(int) * kNumCounters);
     L.off_mask = off;     off = align_up(off + sizeof(int) * (size_t)std::max(n_patches, 1));
+    L.off_sorted = off;   off = align_up(off + sizeof(int4) * items);
+    L.off_keys = off;     off = align_up(off + sizeof(int) * items);
     L.total = off;
     return L;
 }
@@ -457,6 +536,8 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     if (lp->pop_dtype != LBM_F32_SHIFTED && lp->pop_dtype != LBM_F64)
         return set_error(LBM_EINVAL, std::string(fn) + "unknown pop_dtype");
     if (lp->avg_margin < 0) return set_error(LBM_EINVAL, std::string(fn) + "avg_margin must be >= 0");
+    if (lp->schedule != LBM_SCHEDULE_GIVEN && lp->schedule != LBM_SCHEDULE_COST)
+        return set_error(LBM_EINVAL, std::string(fn) + "unknown schedule");
     if (n_patches < 0) return set_error(LBM_EINVAL, std::string(fn) + "n_patches < 0");
     if (n_patches == 0) return LBM_OK;
     if (!h_x0 || !h_y0 || !h_side || !h_drive_mask || !d_kappa_field || !d_keff)
@@ -543,14 +624,31 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
         LBM_HIP(hipMemcpyAsync(d_classes, classes.data(), sizeof(ClassDesc) * classes.size(),
                                hipMemcpyHostToDevice, stream));
     LBM_HIP(hipMemcpyAsync(d_mask, h_drive_mask, sizeof(int) * n_patches, hipMemcpyHostToDevice, stream));
-    const int nfill = std::max(n_patches, kMaxClasses);
+    const int nfill = std::max(n_patches, kNumCounters);
     hipLaunchKernelGGL(k_local_prefill, dim3((nfill + 255) / 256), dim3(256), 0, stream, n_patches, d_mask,
-                       d_keff, d_steps, d_flags, d_counters, kMaxClasses);
+                       d_keff, d_steps, d_flags, d_counters, kNumCounters);
     LBM_HIP(hipGetLastError());
     if (items.empty()) return LBM_OK;
+    const int4 *d_run = d_items;
+    if (lp->schedule == LBM_SCHEDULE_COST) {
+        const int ni = (int)items.size();
+        int *d_hist = d_counters + kMaxClasses, *d_cursor = d_hist + kHist;
+        int *d_keys = reinterpret_cast<int *>(ws + L.off_keys);
+        int4 *d_sorted = reinterpret_cast<int4 *>(ws + L.off_sorted);
+        hipLaunchKernelGGL(k_local_cost, dim3(ni), dim3(256), 0, stream, d_items, d_classes,
+                           (int)classes.size(), d_kappa_field, fnx, fny, d_keys, d_hist);
+        LBM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_local_scan, dim3(1), dim3(256), 0, stream, d_hist, d_cursor,
+                           (int)classes.size() * kCostBins);
+        LBM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_local_scatter, dim3((ni + 255) / 256), dim3(256), 0, stream, ni, d_items, d_keys,
+                           d_cursor, d_sorted);
+        LBM_HIP(hipGetLastError());
+        d_run = d_sorted;
+    }
 
     LocalArgs a{};
-    a.items = d_items;
+    a.items = d_run;
     a.classes = d_classes;
     a.nclasses = (int)classes.size();
     a.counters = d_counters;

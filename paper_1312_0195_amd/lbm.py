@@ -21,6 +21,7 @@ LBM_OK, LBM_EINVAL, LBM_EDEVICE, LBM_ENOTCONV, LBM_ENONFINITE, LBM_EWORKSPACE = 
 LBM_F32_SHIFTED, LBM_F64 = 0, 1
 LBM_PERM_SCALAR, LBM_PERM_TENSOR = 1, 4
 LBM_SCHEME_SHAN_CHEN, LBM_SCHEME_GUO = 0, 1
+LBM_SCHEDULE_GIVEN, LBM_SCHEDULE_COST = 0, 1
 LBM_KEFF_SCALAR, LBM_KEFF_TENSOR = 0, 1
 
 #: every symbol the header declares (checked against include/lbm.h by the tests)
@@ -62,7 +63,8 @@ class lbm_local_params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("eps", ctypes.c_double), ("nu", ctypes.c_double),
                 ("g", ctypes.c_double), ("tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("max_steps", ctypes.c_int64),
-                ("pop_dtype", ctypes.c_int32), ("avg_margin", ctypes.c_int32)]
+                ("pop_dtype", ctypes.c_int32), ("avg_margin", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class lbm_local_tile(ctypes.Structure):
@@ -532,14 +534,19 @@ class LocalResult:
 def local_keff(kappa_field, x0, y0, side, tau, eps, nu, g=1e-6, tol=1e-6, check_every=100,
                max_steps=200000, drive_mask=None, tiles=None, block_threads=0, device="cuda",
                kappa_dev=None, use_tuned=True, pop_dtype=LBM_F32_SHIFTED,
-               avg_margin=0) -> LocalResult:
+               avg_margin=0, schedule=None) -> LocalResult:
     """Run lbm_local_keff on a field (host array or device tensor) and return
     host results. Without explicit tiles, the autotuned table is used when
-    one exists (see paper_1312_0195_amd.autotune)."""
+    one exists (see paper_1312_0195_amd.autotune); without an explicit
+    schedule, the table's, else LBM_SCHEDULE_COST."""
     import torch
     if tiles is None and block_threads == 0 and use_tuned:
         from .autotune import load_table
         block_threads, tiles = load_table()
+    if schedule is None:
+        from .autotune import load_schedule
+        schedule = load_schedule() if use_tuned else None
+        schedule = LBM_SCHEDULE_COST if schedule is None else schedule
     n = len(x0)
     dev = torch.device(device)
     kd = kappa_dev if kappa_dev is not None else torch.as_tensor(
@@ -550,7 +557,8 @@ def local_keff(kappa_field, x0, y0, side, tau, eps, nu, g=1e-6, tol=1e-6, check_
     nbytes = lbm_local_workspace_bytes(n)
     ws = _workspace(nbytes, dev)
     lp = lbm_local_params(float(tau), float(eps), float(nu), float(g), float(tol),
-                          int(check_every), int(max_steps), int(pop_dtype), int(avg_margin))
+                          int(check_every), int(max_steps), int(pop_dtype), int(avg_margin),
+                          int(schedule))
     dm = np.full(n, 3, np.int32) if drive_mask is None else drive_mask
     lbm_local_keff(lp, x0, y0, side, dm, kd, keff, steps, flags, tiles, block_threads, ws,
                    nbytes)

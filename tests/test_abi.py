@@ -105,6 +105,25 @@ def test_local_rejects_bad_avg_margin_on_host():
         assert b"avg_margin" in L.lib().lbm_last_error()
 
 
+def test_local_rejects_unknown_schedule_on_host():
+    one = (ctypes.c_int32 * 1)(0)
+    side = (ctypes.c_int32 * 1)(8)
+    mask = (ctypes.c_int32 * 1)(3)
+    fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: validation fails first
+    for sched in (-1, 2):
+        lp = L.lbm_local_params(0.8, 0.4, 0.1, 1e-6, 1e-6, 100, 1000, L.LBM_F32_SHIFTED, 0, sched)
+        st = L.lib().lbm_local_keff(ctypes.byref(lp), 1, one, one, side, mask, fake, 8, 8, fake,
+                                    None, None, None, 0, 0, fake, 1 << 20, None)
+        assert st == L.LBM_EINVAL, sched
+        assert b"schedule" in L.lib().lbm_last_error()
+
+
+def test_local_workspace_grows_with_patches():
+    a, b = L.lbm_local_workspace_bytes(1), L.lbm_local_workspace_bytes(1000)
+    # per patch: two items and their reordered copy (16 B each), two sort keys, the drive mask
+    assert b - a >= 999 * (2 * 16 + 2 * 16 + 2 * 4 + 4) - 4096
+
+
 def test_d3q19_params_validated_on_host():
     ok = L.make_params3(64, 8, 8, 0.8, 0.4, 0.1)
     assert L.lbm3d_workspace_bytes(ok) > 2 * 19 * 64 * 8 * 8 * 4

@@ -104,6 +104,34 @@ def test_local_tile_choices_agree(L, block_threads):
         assert np.allclose(r.keff, ref.keff, rtol=1e-6, atol=1e-9)
 
 
+def test_local_schedule_changes_only_the_order(L):
+    # Items are independent: the start order (given, or longest predicted
+    # first) and the order of the patch arrays must not change any result bit.
+    field = I.lognormal_kappa(160, 96, 1.8, 6.0, seed=21)
+    field[40:44, 100:104] = np.inf   # no drag
+    field[80, 10] = -1.0             # a patch that ends non-finite
+    rng = np.random.default_rng(5)
+    sides = rng.choice([1, 2, 5, 16, 17, 24, 31, 32, 33, 48, 64], 60).astype(np.int32)
+    x0 = rng.integers(0, 160, 60).astype(np.int32)
+    y0 = rng.integers(0, 96, 60).astype(np.int32)
+    # all drag-free (never converges: step cap), one cell with kappa < 0
+    # (non-finite), one wrapping both ways
+    x0[:3], y0[:3], sides[:3] = [100, 9, 150], [40, 78, 90], [4, 8, 24]
+    mask = rng.integers(0, 4, 60).astype(np.int32)
+    mask[:3] = 3
+    kw = dict(tol=GPU_TOL, check_every=100, max_steps=6000, drive_mask=mask)
+    a = L.local_keff(field, x0, y0, sides, TAU, EPS, NU, G, schedule=L.LBM_SCHEDULE_GIVEN, **kw)
+    b = L.local_keff(field, x0, y0, sides, TAU, EPS, NU, G, schedule=L.LBM_SCHEDULE_COST, **kw)
+    perm = rng.permutation(60)
+    kw["drive_mask"] = mask[perm]
+    c = L.local_keff(field, x0[perm], y0[perm], sides[perm], TAU, EPS, NU, G,
+                     schedule=L.LBM_SCHEDULE_COST, **kw)
+    assert {0, 1, 2, -1} <= set(np.unique(a.flags).tolist())  # every outcome is exercised
+    for r, idx in ((b, np.arange(60)), (c, np.argsort(perm))):
+        assert np.array_equal(r.keff[idx], a.keff, equal_nan=True)
+        assert np.array_equal(r.steps[idx], a.steps) and np.array_equal(r.flags[idx], a.flags)
+
+
 def test_local_flags_step_cap_and_bad_kappa(L):
     field = I.lognormal_kappa(32, 32, 1.0, 4.0, seed=1)
     field[3, 4] = -1.0
