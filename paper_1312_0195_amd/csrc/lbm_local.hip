@@ -34,6 +34,12 @@
 //    side's queue is empty and all slots are idle the workgroup moves on to
 //    the next side. Every item runs at most max_steps steps, so every
 //    workgroup reaches the end of the queues and exits.
+//  * Within a side, items start in the order given or (LBM_SCHEDULE_COST)
+//    longest predicted first: step counts span orders of magnitude, and a
+//    long item that starts late sets the end of the whole batch. The
+//    prediction is the patch's arithmetic-mean permeability (the drag term
+//    relaxes the mean flow on the time scale kappa / (eps nu)); a pre-pass
+//    bins it and counting-sorts the item list on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
