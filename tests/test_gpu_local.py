@@ -132,6 +132,20 @@ def test_local_schedule_changes_only_the_order(L):
         assert np.array_equal(r.steps[idx], a.steps) and np.array_equal(r.flags[idx], a.flags)
 
 
+def test_local_schedule_f64_state(L):
+    # FP64 items (sides up to 45) in both start orders: identical results
+    field = I.lognormal_kappa(96, 96, 2.0, 5.0, seed=8)
+    rng = np.random.default_rng(9)
+    sides = rng.choice([3, 8, 16, 24, 32, 45], 24).astype(np.int32)
+    x0 = rng.integers(0, 96, 24).astype(np.int32)
+    y0 = rng.integers(0, 96, 24).astype(np.int32)
+    kw = dict(tol=1e-9, check_every=50, max_steps=20000, pop_dtype=L.LBM_F64)
+    a = L.local_keff(field, x0, y0, sides, 0.53, EPS, NU, G, schedule=L.LBM_SCHEDULE_GIVEN, **kw)
+    b = L.local_keff(field, x0, y0, sides, 0.53, EPS, NU, G, schedule=L.LBM_SCHEDULE_COST, **kw)
+    assert np.array_equal(a.keff, b.keff, equal_nan=True)
+    assert np.array_equal(a.steps, b.steps) and np.array_equal(a.flags, b.flags)
+
+
 def test_local_flags_step_cap_and_bad_kappa(L):
     field = I.lognormal_kappa(32, 32, 1.0, 4.0, seed=1)
     field[3, 4] = -1.0
