@@ -224,9 +224,11 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
 // BF16 copies of conv2..4 weights:
 //   wf[l][tap][co][ci]  (forward B operand: 8 consecutive ci per lane)
 //   wb[l][tap][ci][co]  (backward-data B operand: 8 consecutive co per lane)
-__global__ void k_pack(const float *__restrict__ prm, __bf16 *__restrict__ wf, __bf16 *__restrict__ wb)
+__global__ void k_pack(const float *__restrict__ prm, __bf16 *__restrict__ wf, __bf16 *__restrict__ wb,
+                       int *__restrict__ next)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *next = 0;  // patch counter of the following forward launch
     if (i >= 3 * 9 * kC * kC) return;
     const int l = i / (9 * kC * kC), r = i % (9 * kC * kC);
     const int tap = r / (kC * kC), ci = (r / kC) % kC, co = r % kC;
@@ -246,6 +248,7 @@ struct FwdArgs {
     float *stats;           // [B][8] mean, std, lag-1 corr x, y, the 4 features (or null)
     __bf16 *acts;           // [4][B][1024][32] when training, else null
     float *pool_out;        // [B][37] head input when training
+    int *next;              // patches claimed beyond the first gridDim.x (zeroed by k_pack)
 };
 
 // One 3x3, 32 -> 32 layer on MFMA. in/out are [pixel][channel] BF16 in LDS.
@@ -349,7 +352,11 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     const int tid = threadIdx.x;
     const float *prm = a.prm;
 
-    for (int b = blockIdx.x; b < a.batch; b += gridDim.x) {
+    // Patches are claimed one at a time (each workgroup starts with its own
+    // index, then takes the next free one), so workgroups that start late --
+    // behind other work on the device -- simply take fewer patches.
+    __shared__ int claimed;
+    for (int b = blockIdx.x; b < a.batch;) {
         const float *lk = a.logk + (size_t)b * kPix;
         float acc0 = 0.0f, acc1 = 0.0f;  // averaged prediction (thread 0)
         for (int t = 0; t < a.n_sym; ++t) {
@@ -442,7 +449,12 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
         if (tid == 0) {
             a.pred[2 * (size_t)b] = acc0 / a.n_sym;
             a.pred[2 * (size_t)b + 1] = acc1 / a.n_sym;
+            claimed = (int)gridDim.x + atomicAdd(a.next, 1);
         }
+        // every thread reads the claim before the next write to it, which
+        // comes after the barriers of the next patch
+        __syncthreads();
+        b = claimed;
     }
 }
 
@@ -758,8 +770,8 @@ __global__ void k_adam(float *__restrict__ prm, float *__restrict__ mom, float *
 }
 
 struct SurLayout {
-    size_t off_wf, off_wb, off_acts, off_pool, off_dpool, off_ghead, off_loss_terms, off_gpart, off_grad,
-        off_loss, off_pred, total;
+    size_t off_wf, off_wb, off_next, off_acts, off_pool, off_dpool, off_ghead, off_loss_terms, off_gpart,
+        off_grad, off_loss, off_pred, total;
     int grid;
 };
 
@@ -771,6 +783,7 @@ SurLayout sur_layout(int batch, bool train)
     size_t off = 0;
     L.off_wf = off; off = align_up(off + 3 * 9 * kC * kC * 2);
     L.off_wb = off; off = align_up(off + 3 * 9 * kC * kC * 2);
+    L.off_next = off; off = align_up(off + sizeof(int));
     if (train) {
         L.off_acts = off;       off = align_up(off + 4 * B * kPix * kC * 2);
         L.off_pool = off;       off = align_up(off + B * kZ * 4);
@@ -801,7 +814,8 @@ lbm_status pack(const float *prm, char *ws, const SurLayout &L, hipStream_t stre
 {
     const int n = 3 * 9 * kC * kC;
     hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, stream, prm,
-                       reinterpret_cast<__bf16 *>(ws + L.off_wf), reinterpret_cast<__bf16 *>(ws + L.off_wb));
+                       reinterpret_cast<__bf16 *>(ws + L.off_wf), reinterpret_cast<__bf16 *>(ws + L.off_wb),
+                       reinterpret_cast<int *>(ws + L.off_next));
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -820,6 +834,7 @@ lbm_status forward(const float *prm, int batch, const float *logk, const int8_t 
     a.stats = stats;
     a.acts = train ? reinterpret_cast<__bf16 *>(ws + L.off_acts) : nullptr;
     a.pool_out = train ? reinterpret_cast<float *>(ws + L.off_pool) : nullptr;
+    a.next = reinterpret_cast<int *>(ws + L.off_next);
     LBM_HIP(hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds));
     const int grid = std::max(1, std::min(batch, device_cu_count()));
     hipLaunchKernelGGL(k_forward, dim3(grid), dim3(kT), kFwdLds, stream, a);

@@ -123,11 +123,18 @@ def detector_features(stats) -> np.ndarray:
     difference (anisotropy, e.g. channels), and when present the gap between
     the upper and lower estimate in each direction (contrast and its
     connectivity) and the difference of the two upper estimates."""
-    s = np.asarray(stats, dtype=np.float64)
-    cols = [s[:, 1], s[:, 2], s[:, 3], s[:, 2] - s[:, 3]]
+    return np.stack(list(_feature_columns(np.asarray(stats, dtype=np.float64))), axis=1)
+
+
+def _feature_columns(s):
+    yield s[:, 1]
+    yield s[:, 2]
+    yield s[:, 3]
+    yield s[:, 2] - s[:, 3]
     if s.shape[1] >= 8:
-        cols += [s[:, 5] - s[:, 4], s[:, 7] - s[:, 6], s[:, 5] - s[:, 7]]
-    return np.stack(cols, axis=1)
+        yield s[:, 5] - s[:, 4]
+        yield s[:, 7] - s[:, 6]
+        yield s[:, 5] - s[:, 7]
 
 
 @dataclass
@@ -221,8 +228,14 @@ class Surrogate:
         return np.concatenate(preds).astype(np.float64), np.concatenate(stats).astype(np.float64)
 
     def in_range(self, stats) -> np.ndarray:
-        s = detector_features(stats)[:, :len(self.stat_lo)]
-        return ((s >= self.stat_lo) & (s <= self.stat_hi)).all(axis=1)
+        # column by column (no feature matrix): the same comparisons as
+        # against detector_features(stats), without its copies
+        s = np.asarray(stats, dtype=np.float64)
+        ok = np.ones(len(s), bool)
+        for j, col in zip(range(len(self.stat_lo)), _feature_columns(s)):
+            ok &= col >= self.stat_lo[j]
+            ok &= col <= self.stat_hi[j]
+        return ok
 
     def save(self, path):
         np.savez(path, params=self.params, stat_lo=self.stat_lo, stat_hi=self.stat_hi,
@@ -235,12 +248,35 @@ class Surrogate:
                    list(d["history"]), int(d["n_sym"]) if "n_sym" in d else 8)
 
 
-def keff_with_fallback(model: Surrogate, kappa_dev, x0, y0, logk_dev, n_sym=None):
+def _local_keff_launch(kappa_dev, x0, y0, tol=1e-7):
+    """Enqueue lbm_local_keff for 32 x 32 windows on the current stream
+    without waiting; returns the device K_eff tensor [n, 4] (and the buffers
+    that must outlive the launch)."""
+    import torch
+    from .autotune import load_schedule, load_table
+    n = len(x0)
+    dev = kappa_dev.device
+    block, tiles = load_table()
+    sched = load_schedule()
+    keff = torch.empty((n, 4), dtype=torch.float64, device=dev)
+    nb = L.lbm_local_workspace_bytes(n)
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+    lp = L.lbm_local_params(PHYS["tau"], PHYS["eps"], PHYS["nu"], PHYS["g"], float(tol), 100, 400000,
+                            L.LBM_F32_SHIFTED, 0, L.LBM_SCHEDULE_COST if sched is None else sched)
+    L.lbm_local_keff(lp, x0, y0, np.full(n, SIDE, np.int32), np.full(n, 3, np.int32), kappa_dev, keff,
+                     None, None, tiles, block, ws, nb)
+    return keff, ws
+
+
+def keff_with_fallback(model: Surrogate, kappa_dev, x0, y0, logk_dev, n_sym=None, lbm_first=True):
     """log kxx, log kyy of the 32 x 32 windows at (x0, y0) of the device field
     kappa_dev, whose log patches are logk_dev (FP32 [n, 32, 32], device):
     the network where a patch is in range, the batched LBM where it is not.
-    The patch statistics come first (lbm_patch_stats); the network then runs
-    on a second stream while the LBM solves the flagged patches.
+    The patch statistics come first (lbm_patch_stats); then the LBM for the
+    flagged patches and the network run on two streams. With lbm_first the
+    LBM is enqueued first, so its persistent launch holds the CUs and the
+    network's workgroups (which claim patches dynamically) fill the CUs the
+    LBM's last, longest items leave idle.
     Returns (log_keff [n, 2], used_lbm [n] bool, seconds)."""
     import torch
     n = len(x0)
@@ -252,18 +288,28 @@ def keff_with_fallback(model: Surrogate, kappa_dev, x0, y0, logk_dev, n_sym=None
     nb = L.lbm_cnn_workspace_bytes(n, False)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     side = torch.cuda.Stream(device=dev)
+    main = torch.cuda.current_stream(dev)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     L.lbm_patch_stats(n, logk_dev, st)
     ok = model.in_range(st.cpu().numpy().astype(np.float64))
-    side.wait_stream(torch.cuda.current_stream(dev))
-    with torch.cuda.stream(side):
-        L.lbm_cnn_forward(prm, n, logk_dev, n_sym, pred, None, ws, nb)
-    y = None
+    keff = None
+    side.wait_stream(main)  # the network needs only what is on the main stream so far
+
+    def network():
+        with torch.cuda.stream(side):
+            L.lbm_cnn_forward(prm, n, logk_dev, n_sym, pred, None, ws, nb)
+
+    if not lbm_first:
+        network()
     if (~ok).any():
-        y, _ = label_patches(None, x0[~ok], y0[~ok], kappa_dev=kappa_dev)
+        keff, _keep = _local_keff_launch(kappa_dev, x0[~ok], y0[~ok])
+    if lbm_first:
+        network()
     torch.cuda.synchronize(dev)
     out = pred.cpu().numpy().astype(np.float64)
-    if y is not None:
-        out[~ok] = y
+    if keff is not None:
+        k = keff.cpu().numpy()
+        out[~ok, 0] = np.log(k[:, 0])
+        out[~ok, 1] = np.log(k[:, 3])
     return out, ~ok, time.perf_counter() - t0

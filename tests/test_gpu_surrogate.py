@@ -268,14 +268,15 @@ def test_pipelined_fallback_matches_separate_paths(L):
     kd = torch.as_tensor(big).cuda()
     logk = np.stack([np.log(I.cut_patch(big, a, b, 32)) for a, b in zip(x0, y0)]).astype(np.float32)
     xd = torch.as_tensor(logk).cuda()
-    out, used, secs = S.keff_with_fallback(model, kd, x0, y0, xd)
     pred, stats = model.predict(logk)
     ok = model.in_range(stats)
-    assert (used == ~ok).all() and used.any() and (~used).any()
-    assert np.array_equal(out[ok], pred[ok])
     y_lbm, _ = S.label_patches(None, x0[~ok], y0[~ok], kappa_dev=kd)
-    assert np.allclose(out[~ok], y_lbm, rtol=0, atol=1e-12)
-    assert secs > 0
+    for lbm_first in (True, False):  # either launch order: same results
+        out, used, secs = S.keff_with_fallback(model, kd, x0, y0, xd, lbm_first=lbm_first)
+        assert (used == ~ok).all() and used.any() and (~used).any()
+        assert np.array_equal(out[ok], pred[ok])
+        assert np.allclose(out[~ok], y_lbm, rtol=0, atol=1e-12)
+        assert secs > 0
 
 
 def test_trained_network_gains_over_the_method_without_it(L):
