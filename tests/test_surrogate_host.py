@@ -59,3 +59,20 @@ def test_detector_uses_series_parallel_gaps():
     m = S.Surrogate(S.init_params(), np.array([0.5, 0.8, 0.8, -0.05, 0.0, 0.0, -1.0]),
                     np.array([3.0, 1.0, 1.0, 0.05, 1.0, 1.0, 1.0]))
     assert list(m.in_range(st)) == [True, False]
+
+
+def test_range_detector_equals_the_feature_matrix_test():
+    """in_range (column by column) flags exactly the rows whose detector
+    features leave [stat_lo, stat_hi], NaN rows included, for the committed
+    model's bounds and for a model that bounds only the first four features."""
+    rng = np.random.default_rng(4)
+    st = rng.normal(size=(5000, 8)) * 0.6 + np.array([0, 1, 0.9, 0.9, -0.3, 0.3, -0.3, 0.3])
+    st[::37, rng.integers(0, 8)] = np.nan
+    m = S.Surrogate.load(T.DEFAULT_MODEL)
+    short = S.Surrogate(S.init_params(), np.array([0.5, 0.8, 0.8, -0.05]), np.array([3.0, 1.0, 1.0, 0.05]))
+    for model in (m, short):
+        f = S.detector_features(st)[:, :len(model.stat_lo)]
+        want = ((f >= model.stat_lo) & (f <= model.stat_hi)).all(axis=1)
+        got = model.in_range(st)
+        assert got.dtype == bool and np.array_equal(got, want)
+        assert 0 < want.sum() < len(want)
