@@ -286,7 +286,9 @@ lbm_status lbm_block_average(const double *d_in, int32_t nx, int32_t ny, int32_t
 int32_t lbm_cnn_param_count(void);
 
 /* Workspace for a batch: training != 0 adds the stored activations and
- * gradient buffers (about 256 KB per patch). */
+ * gradient buffers (about 256 KB per patch). It also holds the packed weights
+ * and the counter from which the forward kernel's workgroups claim patches,
+ * so calls that may run at the same time need workspaces of their own. */
 size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training);
 
 /* The per-patch statistics of lbm_cnn_forward's d_stats alone (same
