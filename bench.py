@@ -183,6 +183,9 @@ def bench_local(L, torch, kappa_dev, reps=3):
         lu = float(np.sum(r.steps.astype(np.float64) * (side.astype(np.float64) ** 2)[:, None]))
         out[name] = dict(patches=int(len(x0)), seconds=best, patches_per_s=len(x0) / best,
                          lattice_updates=lu, mlups=lu / best / 1e6,
+                         # what a step streamed through HBM would need for the same
+                         # updates (76 B each): an on-chip design passes 8 TB/s
+                         hbm_equivalent_gbs=round(lu / best * BYTES_PER_LU / 1e9, 1),
                          converged=int((r.flags == 0).sum()), items=int(r.flags.size),
                          mean_steps=float(r.steps.mean()))
         # on-chip bound: the VALU issue rate over the kernel's measured VALU
