@@ -45,6 +45,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -459,7 +460,7 @@ LocalLayout local_layout(int n_patches)
     size_t off = 0;
     const size_t items = 2 * (size_t)std::max(n_patches, 1);
     L.off_items = off;    off = align_up(off + sizeof(int4) * items);
-    L.off_classes = off;  off = align_up(off + sizeof(ClassDesc) * kMaxClasses);
+    L.off_classes = off;  off = align_up(off + sizeof(ClassDesc) * 2 * kMaxClasses);
     L.off_counters = off; off = align_up(off + sizeof(int) * kNumCounters);
     L.off_mask = off;     off = align_up(off + sizeof(int) * (size_t)std::max(n_patches, 1));
     L.off_sorted = off;   off = align_up(off + sizeof(int4) * items);
@@ -482,6 +483,20 @@ int pow2_at_least(int v)
     int p = 64;
     while (p < v) p <<= 1;
     return p;
+}
+
+// A second stream per device (default priority, created on first use) for
+// running two launches of one call side by side.
+hipStream_t side_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
 }
 
 template <int T, typename P, int CPT>
@@ -681,26 +696,71 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     a.margin = lp->avg_margin;
     const int64_t ms = (lp->max_steps + lp->check_every - 1) / lp->check_every * lp->check_every;
     a.max_steps = (int)std::min<int64_t>(ms, (int64_t)1 << 30);
-    // One persistent launch for all classes (largest side first, so small
-    // items fill the tail of large ones), compiled for the most cells any
-    // thread owns (1, 2 or 4): a launch of small patches only keeps fewer
-    // registers live and fits more workgroups per CU. (Splitting a mixed
-    // launch by register shape loses the shared tail and was slower.)
-    // Within a launch, one workgroup per concurrent slot-set, no more than
-    // the items need.
-    int cmax = 1, need = 0;
-    size_t lds = 0;
-    for (const ClassDesc &c : classes) {
-        cmax = std::max(cmax, c.cells_per_thread);
-        need = std::max(need, (c.count + c.nslots - 1) / c.nslots);
-        lds = std::max(lds, (size_t)c.nslots * cb * c.side * c.side);
+    // One persistent launch per register shape: each is compiled for the most
+    // cells any of its threads owns (1, 2 or 4), since a launch for single
+    // cells keeps fewer registers live and fits two workgroups per CU. When a
+    // call mixes single-cell sides with larger ones, the single-cell sides run
+    // in a launch of their own on a second stream beside the others (joined
+    // back to the caller's stream before the call's later work); run one
+    // after the other, the two launches were slower than one launch for all.
+    // Within a launch, the classes keep their order (largest side first), and
+    // there is one workgroup per concurrent slot-set, no more than the items
+    // need.
+    std::vector<ClassDesc> grouped;
+    grouped.reserve(classes.size());
+    for (const ClassDesc &c : classes)
+        if (c.cells_per_thread > 1) grouped.push_back(c);
+    const int n_multi = (int)grouped.size();
+    for (const ClassDesc &c : classes)
+        if (c.cells_per_thread <= 1) grouped.push_back(c);
+    ClassDesc *d_grouped = d_classes + kMaxClasses;
+    LBM_HIP(hipMemcpyAsync(d_grouped, grouped.data(), sizeof(ClassDesc) * grouped.size(), hipMemcpyHostToDevice,
+                           stream));
+    auto launch_group = [&](int first, int count, hipStream_t st) -> lbm_status {
+        LocalArgs g = a;
+        g.classes = d_grouped + first;
+        g.nclasses = count;
+        g.counters = d_counters + first;
+        int cmax = 1, need = 0;
+        size_t lds = 0;
+        for (int i = first; i < first + count; ++i) {
+            const ClassDesc &c = grouped[i];
+            cmax = std::max(cmax, c.cells_per_thread);
+            need = std::max(need, (c.count + c.nslots - 1) / c.nslots);
+            lds = std::max(lds, (size_t)c.nslots * cb * c.side * c.side);
+        }
+        const int cpt = cmax <= 1 ? 1 : (cmax <= 2 ? 2 : 4);
+        const int grid = std::max(1, need);
+        if (f64)
+            return (T == 256) ? launch_local<256, double>(g, lds, grid, cpt, st)
+                              : launch_local<512, double>(g, lds, grid, cpt, st);
+        if (T == 256) return launch_local<256, float>(g, lds, grid, cpt, st);
+        if (T == 512) return launch_local<512, float>(g, lds, grid, cpt, st);
+        return launch_local<1024, float>(g, lds, grid, cpt, st);
+    };
+    const int n_single = (int)grouped.size() - n_multi;
+    hipStream_t side = (n_multi > 0 && n_single > 0) ? side_stream() : nullptr;
+    if (!side) return launch_group(0, (int)grouped.size(), stream);
+    hipEvent_t fork = nullptr, join = nullptr;
+    LBM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(fork);
+        return set_error(LBM_EDEVICE, std::string(fn) + "hipEventCreateWithFlags failed");
     }
-    const int cpt = cmax <= 1 ? 1 : (cmax <= 2 ? 2 : 4);
-    const int grid = std::max(1, need);
-    if (f64)
-        return (T == 256) ? launch_local<256, double>(a, lds, grid, cpt, stream)
-                          : launch_local<512, double>(a, lds, grid, cpt, stream);
-    if (T == 256) return launch_local<256, float>(a, lds, grid, cpt, stream);
-    if (T == 512) return launch_local<512, float>(a, lds, grid, cpt, stream);
-    return launch_local<1024, float>(a, lds, grid, cpt, stream);
+    lbm_status st = LBM_OK;
+    hipError_t e = hipEventRecord(fork, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e == hipSuccess) {
+        st = launch_group(0, n_multi, stream);
+        if (st == LBM_OK) st = launch_group(n_multi, n_single, side);
+        // join even after a failed launch, so the caller's stream never runs
+        // ahead of work queued on the side stream
+        e = hipEventRecord(join, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, join, 0);
+    }
+    (void)hipEventDestroy(fork);
+    (void)hipEventDestroy(join);
+    if (st != LBM_OK) return st;
+    if (e != hipSuccess) return hip_check(e, "lbm_local_keff: stream fork/join");
+    return LBM_OK;
 }

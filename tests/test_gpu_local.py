@@ -132,6 +132,23 @@ def test_local_schedule_changes_only_the_order(L):
         assert np.array_equal(r.steps[idx], a.steps) and np.array_equal(r.flags[idx], a.flags)
 
 
+def test_local_mixed_call_matches_calls_per_side(L):
+    # A call that mixes single-cell sides with larger ones runs two launches on
+    # two streams; every item must come out as in a call of its side alone.
+    field = I.lognormal_kappa(128, 128, 1.5, 6.0, seed=14)
+    rng = np.random.default_rng(6)
+    sides = rng.choice([8, 16, 24, 32, 40, 48, 64], 70).astype(np.int32)
+    x0 = rng.integers(0, 128, 70).astype(np.int32)
+    y0 = rng.integers(0, 128, 70).astype(np.int32)
+    kw = dict(tol=GPU_TOL, check_every=100, max_steps=8000)
+    both = L.local_keff(field, x0, y0, sides, TAU, EPS, NU, G, **kw)
+    for s in np.unique(sides):
+        m = sides == s
+        one = L.local_keff(field, x0[m], y0[m], sides[m], TAU, EPS, NU, G, **kw)
+        assert np.array_equal(one.keff, both.keff[m], equal_nan=True), s
+        assert np.array_equal(one.steps, both.steps[m]) and np.array_equal(one.flags, both.flags[m]), s
+
+
 def test_local_schedule_f64_state(L):
     # FP64 items (sides up to 45) in both start orders: identical results
     field = I.lognormal_kappa(96, 96, 2.0, 5.0, seed=8)
