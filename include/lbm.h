@@ -140,7 +140,11 @@ void lbm_destroy(lbm_handle *h);
  * velocity converges; then Eq. tensor-kappa gives
  *   kxx = nu ubar1_x / g, kxy = nu ubar2_x / g, kyx = nu ubar1_y / g,
  *   kyy = nu ubar2_y / g.
- * All items of one call run in one persistent launch.
+ * All items of one call run in one persistent launch; when a call mixes sides
+ * that leave one cell per thread with larger ones, in two launches side by
+ * side, the second on a stream the library owns (one per device, default
+ * priority), forked from and joined back to `stream`, so the call stays
+ * ordered on `stream` like a single launch.
  * ------------------------------------------------------------------------- */
 
 typedef struct {
