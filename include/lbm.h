@@ -169,12 +169,14 @@ typedef struct {
 } lbm_local_params;
 
 /* Start order of the local problems. An item's step count varies by orders
- * of magnitude between patches (the mean flow relaxes on the time scale
- * kappa / (eps nu) of the drag term), so a batch ends when its slowest items
- * end. LBM_SCHEDULE_COST starts the items of each side in descending order of
- * the patch's arithmetic-mean permeability (a device pre-pass over the
- * patches, binned at four bins per octave; ties in any order), so the long
- * items start first and the short ones fill in behind them. */
+ * of magnitude between patches, so a batch ends when its slowest items end.
+ * LBM_SCHEDULE_COST starts the items of each side in descending order of a
+ * predicted cost, max(ln mean kappa, 0) + 3 sd(ln kappa) over the patch (a
+ * high mean permeability relaxes slowly, on the time scale kappa / (eps nu)
+ * of the drag term; a strongly heterogeneous patch has nearly blocked
+ * directions whose small velocities converge slowly), computed by a device
+ * pre-pass and binned in steps of 1/2 (ties in any order), so the long items
+ * start first and the short ones fill in behind them. */
 enum {
     LBM_SCHEDULE_GIVEN = 0, /* the order of the patch arrays (within a side) */
     LBM_SCHEDULE_COST = 1   /* longest predicted first */

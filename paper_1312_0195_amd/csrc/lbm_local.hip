@@ -37,9 +37,9 @@
 //  * Within a side, items start in the order given or (LBM_SCHEDULE_COST)
 //    longest predicted first: step counts span orders of magnitude, and a
 //    long item that starts late sets the end of the whole batch. The
-//    prediction is the patch's arithmetic-mean permeability (the drag term
-//    relaxes the mean flow on the time scale kappa / (eps nu)); a pre-pass
-//    bins it and counting-sorts the item list on the device.
+//    prediction combines the patch's mean permeability and the spread of
+//    its logarithm (k_local_cost); a pre-pass bins it and counting-sorts the
+//    item list on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -376,8 +376,11 @@ __global__ void k_local_prefill(int n, const int *__restrict__ mask, double *__r
 
 // ---- start order (LBM_SCHEDULE_COST) --------------------------------------
 // Key of an item: its side class in the high part (classes keep their
-// ranges), then the bin of the patch's arithmetic-mean permeability, largest
-// first: kCostBins bins of a quarter octave each, from 2^-8 up.
+// ranges), then the bin of its predicted cost, largest first. The prediction
+// is max(ln mean kappa, 0) + 3 sd(ln kappa) over the patch: a high mean
+// permeability means a slow relaxation of the mean flow (time scale
+// kappa / (eps nu)), and strong heterogeneity means nearly blocked directions
+// whose tiny velocities converge slowly; kCostBins bins of width 1/2.
 constexpr int kCostBins = 64;
 
 __global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ items,
@@ -385,25 +388,39 @@ __global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ ite
                                                     const double *__restrict__ field, int fnx, int fny,
                                                     int *__restrict__ keys, int *__restrict__ hist)
 {
-    __shared__ double red[4];
+    __shared__ double red[3][4];
     const int item = blockIdx.x;
     const int4 it = items[item];
     const int S = it.z, n = S * S;
-    double sum = 0.0;
+    double sum = 0.0, sl = 0.0, sl2 = 0.0;
     for (int c = threadIdx.x; c < n; c += 256) {
         const int fx = (it.x + c % S) % fnx, fy = (it.y + c / S) % fny;
-        sum += field[(size_t)fy * fnx + fx];
+        const double k = field[(size_t)fy * fnx + fx];
+        const double l = log(k);
+        sum += k;
+        sl += l;
+        sl2 += l * l;
     }
     sum = wave_sum(sum);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    sl = wave_sum(sl);
+    sl2 = wave_sum(sl2);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = sum;
+        red[1][threadIdx.x >> 6] = sl;
+        red[2][threadIdx.x >> 6] = sl2;
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    const double mean = ((red[0] + red[1]) + (red[2] + red[3])) / (double)n;
+    const double inv = 1.0 / (double)n;
+    const double mean = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) * inv;
+    const double ml = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) * inv;
+    const double var = ((red[2][0] + red[2][1]) + (red[2][2] + red[2][3])) * inv - ml * ml;
+    const double score = fmax(log(mean), 0.0) + 3.0 * sqrt(fmax(var, 0.0));
     int bin;
-    if (mean > 0.0 && isfinite(mean))
-        bin = min(kCostBins - 1, max(0, (int)floor(4.0 * log2(mean)) + kCostBins / 2));
+    if (isfinite(score))
+        bin = min(kCostBins - 1, (int)(2.0 * score));
     else
-        bin = (mean > 0.0) ? kCostBins - 1 : 0;  // +inf: no drag, slowest; NaN or <= 0: ends at once
+        bin = (score > 0.0) ? kCostBins - 1 : 0;  // +inf kappa: no drag, slowest; NaN (kappa <= 0): ends at once
     int cls = 0;
     for (int c = 0; c < nclasses; ++c)
         if (item >= classes[c].begin && item < classes[c].begin + classes[c].count) cls = c;
