@@ -420,7 +420,8 @@ __global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ ite
     if (isfinite(score))
         bin = min(kCostBins - 1, (int)(2.0 * score));
     else
-        bin = (score > 0.0) ? kCostBins - 1 : 0;  // +inf kappa: no drag, slowest; NaN (kappa <= 0): ends at once
+        bin = (score > 0.0) ? kCostBins - 1 : 0;  // +inf: a cell without drag, slowest; NaN: negative mean,
+                                                  // the item ends at its first check (non-finite)
     int cls = 0;
     for (int c = 0; c < nclasses; ++c)
         if (item >= classes[c].begin && item < classes[c].begin + classes[c].count) cls = c;
