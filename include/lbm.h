@@ -314,6 +314,16 @@ lbm_status lbm_patch_stats(int32_t batch, const float *d_logk, float *d_stats, h
 lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
                            float *d_pred, float *d_stats, void *d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* lbm_cnn_forward on at most max_workgroups workgroups (0: one per CU, as
+ * lbm_cnn_forward; < 0: LBM_EINVAL). Each workgroup claims patches one at a
+ * time, so fewer workgroups only lower the network's share of the device:
+ * the CUs it leaves free serve work on other streams at once, e.g. the batched
+ * local LBM that the surrogate path runs beside it. Results do not depend on
+ * the cap. */
+lbm_status lbm_cnn_forward_limited(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
+                                   float *d_pred, float *d_stats, int32_t max_workgroups, void *d_ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
 /* Loss = mean over the batch and both outputs of (prediction - target)^2,
  * d_target FP32 [batch][2] (log kxx, log kyy of the untransformed patch).
  * d_sym: int8 [batch] symmetry code applied to each patch (training-time

@@ -821,7 +821,8 @@ lbm_status pack(const float *prm, char *ws, const SurLayout &L, hipStream_t stre
 }
 
 lbm_status forward(const float *prm, int batch, const float *logk, const int8_t *sym, int n_sym, float *pred,
-                   float *stats, char *ws, const SurLayout &L, bool train, hipStream_t stream)
+                   float *stats, char *ws, const SurLayout &L, bool train, hipStream_t stream,
+                   int max_workgroups = 0)
 {
     FwdArgs a{};
     a.prm = prm;
@@ -836,7 +837,8 @@ lbm_status forward(const float *prm, int batch, const float *logk, const int8_t 
     a.pool_out = train ? reinterpret_cast<float *>(ws + L.off_pool) : nullptr;
     a.next = reinterpret_cast<int *>(ws + L.off_next);
     LBM_HIP(hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds));
-    const int grid = std::max(1, std::min(batch, device_cu_count()));
+    const int cap = max_workgroups > 0 ? std::min(max_workgroups, device_cu_count()) : device_cu_count();
+    const int grid = std::max(1, std::min(batch, cap));
     hipLaunchKernelGGL(k_forward, dim3(grid), dim3(kT), kFwdLds, stream, a);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
@@ -898,20 +900,30 @@ extern "C" size_t lbm_cnn_workspace_bytes(int32_t batch, int32_t training)
     return sur_layout(batch, training != 0).total;
 }
 
-extern "C" lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
-                                      float *d_pred, float *d_stats, void *d_ws, size_t ws_bytes,
-                                      hipStream_t stream)
+extern "C" lbm_status lbm_cnn_forward_limited(const float *d_params, int32_t batch, const float *d_logk,
+                                              int32_t n_sym, float *d_pred, float *d_stats,
+                                              int32_t max_workgroups, void *d_ws, size_t ws_bytes,
+                                              hipStream_t stream)
 {
     if (batch < 1 || !d_params || !d_logk || !d_pred)
         return set_error(LBM_EINVAL, "lbm_cnn_forward: batch < 1 or NULL argument");
     if (n_sym < 1 || n_sym > 8) return set_error(LBM_EINVAL, "lbm_cnn_forward: n_sym must lie in [1, 8]");
+    if (max_workgroups < 0) return set_error(LBM_EINVAL, "lbm_cnn_forward: max_workgroups must be >= 0");
     const SurLayout L = sur_layout(batch, false);
     lbm_status s = check_ws(d_ws, ws_bytes, L.total, "lbm_cnn_forward");
     if (s != LBM_OK) return s;
     char *ws = static_cast<char *>(d_ws);
     s = pack(d_params, ws, L, stream);
     if (s != LBM_OK) return s;
-    return forward(d_params, batch, d_logk, nullptr, n_sym, d_pred, d_stats, ws, L, false, stream);
+    return forward(d_params, batch, d_logk, nullptr, n_sym, d_pred, d_stats, ws, L, false, stream,
+                   max_workgroups);
+}
+
+extern "C" lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
+                                      float *d_pred, float *d_stats, void *d_ws, size_t ws_bytes,
+                                      hipStream_t stream)
+{
+    return lbm_cnn_forward_limited(d_params, batch, d_logk, n_sym, d_pred, d_stats, 0, d_ws, ws_bytes, stream);
 }
 
 extern "C" lbm_status lbm_cnn_gradients(const float *d_params, int32_t batch, const float *d_logk,

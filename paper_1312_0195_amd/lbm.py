@@ -31,7 +31,8 @@ EXPORTS = (
     "lbm_local_workspace_bytes", "lbm_local_keff", "lbm_coarse_params",
     "lbm_coarse_workspace_bytes", "lbm_coarse_solve", "lbm_block_average", "lbm_status_str",
     "lbm_last_error",
-    "lbm_cnn_param_count", "lbm_cnn_workspace_bytes", "lbm_cnn_forward", "lbm_cnn_gradients",
+    "lbm_cnn_param_count", "lbm_cnn_workspace_bytes", "lbm_cnn_forward", "lbm_cnn_forward_limited",
+    "lbm_cnn_gradients",
     "lbm_cnn_train_step", "lbm_patch_stats",
     "lbm3d_workspace_bytes", "lbm3d_init", "lbm3d_step", "lbm3d_fields", "lbm3d_get_populations",
     "lbm3d_set_populations", "lbm3d_steps_total", "lbm3d_destroy",
@@ -154,6 +155,9 @@ def lib():
     L.lbm_cnn_forward.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]
     L.lbm_cnn_forward.restype = ctypes.c_int
+    L.lbm_cnn_forward_limited.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
+                                          _vp, ctypes.c_size_t, _vp]
+    L.lbm_cnn_forward_limited.restype = ctypes.c_int
     L.lbm_cnn_gradients.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp]
     L.lbm_cnn_gradients.restype = ctypes.c_int
@@ -364,6 +368,13 @@ def lbm_cnn_forward(d_params, batch, d_logk, n_sym, d_pred, d_stats, d_ws, ws_by
     _raise(lib().lbm_cnn_forward(_ptr(d_params), int(batch), _ptr(d_logk), int(n_sym), _ptr(d_pred),
                                  _ptr(d_stats), _ptr(d_ws), int(ws_bytes), _stream(stream)),
            "lbm_cnn_forward")
+
+
+def lbm_cnn_forward_limited(d_params, batch, d_logk, n_sym, d_pred, d_stats, max_workgroups, d_ws,
+                            ws_bytes, stream=None) -> None:
+    _raise(lib().lbm_cnn_forward_limited(_ptr(d_params), int(batch), _ptr(d_logk), int(n_sym),
+                                         _ptr(d_pred), _ptr(d_stats), int(max_workgroups), _ptr(d_ws),
+                                         int(ws_bytes), _stream(stream)), "lbm_cnn_forward_limited")
 
 
 def lbm_cnn_gradients(d_params, batch, d_logk, d_sym, d_target, d_grad, d_loss, d_pred, d_ws,

@@ -187,3 +187,10 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_cnn_forward_limited_rejects_negative_cap_on_host():
+    fake = ctypes.c_void_p(256 * 1024)  # never dereferenced: validation fails first
+    st = L.lib().lbm_cnn_forward_limited(fake, 4, fake, 1, fake, None, -1, fake, 1 << 20, None)
+    assert st == L.LBM_EINVAL
+    assert b"max_workgroups" in L.lib().lbm_last_error()

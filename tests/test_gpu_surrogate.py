@@ -257,6 +257,31 @@ def test_patch_stats_equal_forward_stats(L):
         L.lbm_patch_stats(0, xd, st_s)
 
 
+def test_forward_with_fewer_workgroups_is_identical(L):
+    """lbm_cnn_forward_limited: any cap on the workgroups gives the same bits
+    (each workgroup claims patches one at a time; a patch's arithmetic does
+    not depend on which workgroup runs it)."""
+    from paper_1312_0195_amd import surrogate as S
+    from paper_1312_0195_amd import train_surrogate as T
+    model = S.Surrogate.load(T.DEFAULT_MODEL)
+    n = 777
+    x = torch.randn((n, 32, 32), generator=torch.Generator().manual_seed(3)).cuda()
+    prm = torch.as_tensor(model.params).cuda()
+    nb = L.lbm_cnn_workspace_bytes(n, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    ref = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    rst = torch.empty((n, 8), dtype=torch.float32, device="cuda")
+    L.lbm_cnn_forward(prm, n, x, 2, ref, rst, ws, nb)
+    for cap in (1, 5, 96, 4096, 0):
+        out = torch.empty_like(ref)
+        st = torch.empty_like(rst)
+        L.lbm_cnn_forward_limited(prm, n, x, 2, out, st, cap, ws, nb)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref) and torch.equal(st, rst), cap
+    with pytest.raises(L.LbmError):
+        L.lbm_cnn_forward_limited(prm, n, x, 2, out, st, -1, ws, nb)
+
+
 def test_pipelined_fallback_matches_separate_paths(L):
     """keff_with_fallback (statistics, then the network on a second stream
     concurrent with the LBM on the flagged patches) returns the network's
@@ -271,8 +296,9 @@ def test_pipelined_fallback_matches_separate_paths(L):
     pred, stats = model.predict(logk)
     ok = model.in_range(stats)
     y_lbm, _ = S.label_patches(None, x0[~ok], y0[~ok], kappa_dev=kd)
-    for lbm_first in (True, False):  # either launch order: same results
-        out, used, secs = S.keff_with_fallback(model, kd, x0, y0, xd, lbm_first=lbm_first)
+    for lbm_first, wg in ((True, 0), (False, 0), (False, 96)):  # launch order and cap: same results
+        out, used, secs = S.keff_with_fallback(model, kd, x0, y0, xd, lbm_first=lbm_first,
+                                               network_workgroups=wg)
         assert (used == ~ok).all() and used.any() and (~used).any()
         assert np.array_equal(out[ok], pred[ok])
         assert np.allclose(out[~ok], y_lbm, rtol=0, atol=1e-12)
