@@ -171,7 +171,7 @@ typedef struct {
 /* Start order of the local problems. An item's step count varies by orders
  * of magnitude between patches, so a batch ends when its slowest items end.
  * LBM_SCHEDULE_COST starts the items of each side in descending order of a
- * predicted cost, max(ln mean kappa, 0) + 3 sd(ln kappa) over the patch (a
+ * predicted cost, max(ln mean kappa, 0) + 1.5 sd(ln kappa) over the patch (a
  * high mean permeability relaxes slowly, on the time scale kappa / (eps nu)
  * of the drag term; a strongly heterogeneous patch has nearly blocked
  * directions whose small velocities converge slowly), computed by a device

@@ -377,7 +377,7 @@ __global__ void k_local_prefill(int n, const int *__restrict__ mask, double *__r
 // ---- start order (LBM_SCHEDULE_COST) --------------------------------------
 // Key of an item: its side class in the high part (classes keep their
 // ranges), then the bin of its predicted cost, largest first. The prediction
-// is max(ln mean kappa, 0) + 3 sd(ln kappa) over the patch: a high mean
+// is max(ln mean kappa, 0) + 1.5 sd(ln kappa) over the patch: a high mean
 // permeability means a slow relaxation of the mean flow (time scale
 // kappa / (eps nu)), and strong heterogeneity means nearly blocked directions
 // whose tiny velocities converge slowly; kCostBins bins of width 1/2.
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ ite
     const double mean = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) * inv;
     const double ml = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) * inv;
     const double var = ((red[2][0] + red[2][1]) + (red[2][2] + red[2][3])) * inv - ml * ml;
-    const double score = fmax(log(mean), 0.0) + 3.0 * sqrt(fmax(var, 0.0));
+    const double score = fmax(log(mean), 0.0) + 1.5 * sqrt(fmax(var, 0.0));
     int bin;
     if (isfinite(score))
         bin = min(kCostBins - 1, (int)(2.0 * score));
