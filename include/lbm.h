@@ -198,7 +198,7 @@ int32_t lbm_local_max_side(void);
 size_t lbm_local_workspace_bytes(int32_t n_patches);
 
 /* h_x0, h_y0, h_side, h_drive_mask: HOST int32 arrays of n_patches entries
- *   (origin of the window in the field, side in [2, lbm_local_max_side()],
+ *   (origin of the window in the field, side in [1, lbm_local_max_side()],
  *   drive bits: 1 = x drive, 2 = y drive).
  * d_kappa_field: device FP64 [fny][fnx]; windows wrap periodically.
  * d_keff : device FP64 [n_patches][4] = kxx, kxy, kyx, kyy (entries of a

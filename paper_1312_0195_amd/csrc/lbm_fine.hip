@@ -1,9 +1,11 @@
 // lbm_fine.hip -- fine-grid solver of liblbm (Sec. 2.2 of the paper).
 //
-// One time step is ONE kernel pass over HBM: every cell pulls its nine
-// incoming post-collision populations from its neighbours (streaming of Eq.
-// f-evolution-of-S-C read backwards), collides them in registers and writes
-// the nine new post-collision values to its own cell in the other buffer.
+// A time step is a pull: every cell pulls its nine incoming post-collision
+// populations from its neighbours (streaming of Eq. f-evolution-of-S-C read
+// backwards), collides them in registers and writes the nine new
+// post-collision values to its own cell. k_step does one step per pass over
+// HBM; k_stepd does D = 2, 4 or 6 steps per pass, the intermediate steps
+// staying in LDS (temporal blocking, bit-identical to D single steps).
 // The state in memory is therefore the post-collision populations of the
 // previous step; the pre-collision populations at the current step are the
 // pulled ones, which is what lbm_fields and lbm_get_populations report.

@@ -5,7 +5,7 @@
 // patch to log K_eff (xx and yy), the quantity the local problems of Sec. 3
 // compute with Eq. tensor-kappa:
 //   m = mean(log K), x = log K - m                    (FP32)
-//   a1 = relu(conv3x3(x))      1 -> 32 channels      (FP32 VALU: 9-deep)
+//   a1 = relu(conv3x3(x))      1 -> 32 channels      (BF16 MFMA, the 9 taps as K)
 //   a2..a4 = relu(conv3x3(.))  32 -> 32 channels     (BF16 MFMA, FP32 accumulate)
 //   p = mean over pixels of a4                       (FP32)
 //   s = log series/parallel estimates of exp(x)      (FP32, 4 values:

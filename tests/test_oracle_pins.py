@@ -526,6 +526,55 @@ def test_flux_conservation_eqs_conserve_u():
         assert np.allclose(ux, u_ex[0], rtol=1e-7) and np.allclose(uy, u_ex[1], rtol=1e-7)
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("tau", [0.5, 0.8, 1.3])
+def test_uniform_nonsymmetric_tensor_steady_state(tau, scheme):
+    """Eq. f-steady with the tensor drag of Eq. f_m-depends-on-u-and-tensor-k:
+    a constant tensor K on a periodic lattice has the uniform steady state
+    where the drag balances the force, u = K G / nu (K G, not K^T G), for
+    both drives and in both the Shan-Chen and the Guo form. The tensor is
+    deliberately non-symmetric so that an exchanged kxy / kyx shows."""
+    K = np.array([[1.3, 0.2], [0.1, 0.7]])
+    eps, nu = 0.4, 0.1
+    nx, ny = 5, 4
+    kt = np.broadcast_to(K.reshape(4), (ny, nx, 4)).copy()
+    p = O.Params(nx=nx, ny=ny, tau=tau, eps=eps, nu=nu, perm_kind=4, scheme=scheme)
+    ex, ey, w, _ = O.lattice()
+    for G in [(1e-6, 0.0), (0.0, 1e-6)]:
+        res = O.run(p, kt, G, max_steps=400000, check_every=50, tol=1e-14)
+        assert res.status == O.OK
+        u_ex = K @ np.array(G) / nu
+        _, ux, uy = O.moments(p, kt, res.f, G)
+        assert np.allclose(ux, u_ex[0], rtol=1e-8, atol=1e-8 * np.abs(u_ex).max())
+        assert np.allclose(uy, u_ex[1], rtol=1e-8, atol=1e-8 * np.abs(u_ex).max())
+        f_ex = w * (1 + 3 * (ex * u_ex[0] + ey * u_ex[1]))
+        assert np.allclose(res.f - w, (f_ex - w)[None, None, :], rtol=1e-6, atol=1e-13)
+
+
+@pytest.mark.parametrize("tau", [0.5, 0.8, 1.3])
+def test_guo_form_equals_shan_chen_form_tensor(tau):
+    """Sec. 2.1 vs Sec. 2.2 with a heterogeneous, non-symmetric tensor drag:
+    with the linear f_eq the two forms give the same populations, whatever
+    f_m is, provided rho u = j + rho f_m(u) / 2 holds, so the Guo form's drag
+    force and the Shan-Chen form's velocity solve must use the same tensor."""
+    rng = np.random.default_rng(21)
+    nx, ny = 7, 6
+    kt = np.empty((ny, nx, 4))
+    kt[..., 0] = np.exp(rng.standard_normal((ny, nx)))
+    kt[..., 3] = np.exp(rng.standard_normal((ny, nx)))
+    kt[..., 1] = 0.3 * kt[..., 0] * rng.uniform(-1, 1, (ny, nx))
+    kt[..., 2] = 0.3 * kt[..., 3] * rng.uniform(-1, 1, (ny, nx))
+    force = 1e-4 * rng.standard_normal((ny, nx, 2))
+    psc = O.Params(nx=nx, ny=ny, tau=tau, eps=0.6, nu=0.2, perm_kind=4, scheme=0)
+    pgu = O.Params(nx=nx, ny=ny, tau=tau, eps=0.6, nu=0.2, perm_kind=4, scheme=1)
+    f = _rand_state(psc, 4)
+    for _ in range(10):
+        a = O.step(psc, kt, f, force=force)
+        b = O.step(pgu, kt, f, force=force)
+        assert np.max(np.abs(a - b)) < 1e-15
+        f = a
+
+
 # ---------------------------------------------------------------------------
 # Error handling and helpers
 # ---------------------------------------------------------------------------
