@@ -40,6 +40,10 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions per second (one per 4 cycles per SIMD)
 BYTES_PER_LU = 76  # per cell and launch: 9 x 4 B read + 9 x 4 B written + 4 B drag coefficient
 FLOPS_PER_LU = 65  # FP64 operations of one collision as the kernel writes it (FMA = 2)
+# the local solver's collision in FP32: the same 65 operations (FMA = 2)
+FP32_FLOPS_PER_LU_LOCAL = 65
+FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (published; counts packed FP32 issue)
+FP32_UNPACKED_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2: packed FP32 is not used
 DEPTH = 6          # time steps per launch of the fine-step kernel (FP32 state)
 STEP_KERNEL_SRC = os.path.join(ROOT, "paper_1312_0195_amd", "csrc", "lbm_fine.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fine_step_2048_hbm_counters.md")
@@ -80,15 +84,32 @@ def _valu_per_launch():
     return _summary_value(VALU_SUMMARY, r"SQ_INSTS_VALU per launch:\s*([0-9.eE+]+)")
 
 
-def bench_fine(L, torch, kappa, steps, warmup, check_every=100):
+KERNEL_WARMUP_LAUNCHES = 900  # ~0.1 s of back-to-back step launches before the kernel-alone timing
+KERNEL_LAUNCHES = 360         # launches timed for the kernel-alone roofline (fixed, whatever --steps)
+
+
+def bench_fine(L, torch, kappa, steps, warmup, check_every=100, repeats=5):
     n = kappa.shape[0]
     p = L.make_params(n, n, 0.8, 0.4, 0.1, 1.0, 1e-6, 0.0, 1, L.LBM_F32_SHIFTED)
-    s = L.FineSolver(p, kappa)
     stream = torch.cuda.current_stream()
-    # warm-up: the same mix of step and reduction kernels
+    # step kernel alone, first (so the device is also warm for the timed
+    # region): a fixed number of back-to-back launches of the multi-step
+    # kernel (no reductions, same stream) after a fixed warm-up, independent
+    # of --steps / --warmup, on a solver of its own
+    s = L.FineSolver(p, kappa)
+    s.step(KERNEL_WARMUP_LAUNCHES * DEPTH, 0.0, 0)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record(stream)
+    s.step(KERNEL_LAUNCHES * DEPTH, 0.0, 0)
+    e3.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e2.elapsed_time(e3) / KERNEL_LAUNCHES  # per launch (DEPTH time steps)
+    s.close()
+    # the workload from rest: W warm-up steps, then the timed K steps with the
+    # FP64 mean-velocity reduction every 100 steps
+    s = L.FineSolver(p, kappa)
     s.step(warmup, 0.0, check_every)
     torch.cuda.synchronize()
-    # timed region: K steps with the FP64 mean-velocity reduction every 100 steps
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
@@ -98,17 +119,17 @@ def bench_fine(L, torch, kappa, steps, warmup, check_every=100):
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     assert st == L.LBM_OK and done == steps and np.isfinite(mu).all()
-    # step kernel alone: back-to-back launches of the multi-step kernel, no
-    # reductions, same stream (k a multiple of DEPTH: k / DEPTH launches)
-    k = max(DEPTH, min(steps, 2400) // DEPTH * DEPTH)
-    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e2.record(stream)
-    s.step(k, 0.0, 0)
-    e3.record(stream)
-    torch.cuda.synchronize()
-    step_ms = e2.elapsed_time(e3) / (k // DEPTH)  # per launch (DEPTH time steps)
+    # the same K steps again, for the spread over runs (median of `repeats`)
+    runs = [ev_ms]
+    for _ in range(repeats - 1):
+        e0.record(stream)
+        s.step(steps, 0.0, check_every)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1))
     s.close()
-    return dict(wall_s=wall, event_ms=ev_ms, step_kernel_ms=step_ms, mean_u=mu.tolist())
+    return dict(wall_s=wall, event_ms=ev_ms, run_ms=runs, step_kernel_ms=step_ms,
+                mean_u=mu.tolist())
 
 
 def bench_forms(L, torch, kappa, steps=2000):
@@ -162,44 +183,102 @@ def bench_paper_sec41(L, torch):
         sec = e0.elapsed_time(e1) * 1e-3
         out[name + "_seconds"] = round(sec, 3)
         s.close()
-    out["speedup_vs_paper_shan_chen_f64"] = round(21 * 60 / out["shan_chen_f64_seconds"], 1)
     return out
 
 
-def bench_local(L, torch, kappa_dev, reps=3):
+def bench_local(L, torch, kappa_dev, reps=5, sets=None):
+    """Batched local problems (Sec. 3, Eq. tensor-kappa) on the fine field's
+    4096 tiles of 32 x 32 and on 4096 patches of mixed sides: `reps` calls
+    each, median and best wall time around the whole call (inputs resident)."""
     from paper_1312_0195_amd import inputs as I
     n = kappa_dev.shape[0]
     out = {}
-    sets = {"tiles32": I.tile_patches(n, n, 32), "mixed": I.mixed_patches(4096, n, n, seed=1)}
+    if sets is None:
+        sets = {"tiles32": I.tile_patches(n, n, 32), "mixed": I.mixed_patches(4096, n, n, seed=1)}
+    keff_tiles = None
     for name, (x0, y0, side) in sets.items():
-        best = None
+        times = []
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = L.local_keff(None, x0, y0, side, 0.8, 0.4, 0.1, 1e-6, tol=1e-7, check_every=100,
                              max_steps=400000, kappa_dev=kappa_dev)
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
+            times.append(time.perf_counter() - t0)
+        med, best = float(np.median(times)), min(times)
         lu = float(np.sum(r.steps.astype(np.float64) * (side.astype(np.float64) ** 2)[:, None]))
-        out[name] = dict(patches=int(len(x0)), seconds=best, patches_per_s=len(x0) / best,
-                         lattice_updates=lu, mlups=lu / best / 1e6,
+        flops = FP32_FLOPS_PER_LU_LOCAL * lu / med / 1e12
+        out[name] = dict(patches=int(len(x0)), seconds_median=round(med, 5),
+                         seconds_best=round(best, 5), runs=len(times),
+                         patches_per_s=len(x0) / med, patches_per_s_best=len(x0) / best,
+                         lattice_updates=lu, mlups=lu / med / 1e6,
                          # what a step streamed through HBM would need for the same
                          # updates (76 B each): an on-chip design passes 8 TB/s
-                         hbm_equivalent_gbs=round(lu / best * BYTES_PER_LU / 1e9, 1),
+                         hbm_equivalent_gbs=round(lu / med * BYTES_PER_LU / 1e9, 1),
                          converged=int((r.flags == 0).sum()), items=int(r.flags.size),
-                         mean_steps=float(r.steps.mean()))
-        # on-chip bound: the VALU issue rate over the kernel's measured VALU
-        # lane instructions per lattice update (committed counter summary)
+                         mean_steps=float(r.steps.mean()),
+                         # the collisions' FP32 arithmetic against the vector FP32 peak
+                         roofline={"bound": "alu", "achieved": round(flops, 2),
+                                   "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(flops / FP32_PEAK_TFLOPS, 4),
+                                   "frac_of_unpacked_fp32": round(flops / FP32_UNPACKED_TFLOPS, 4),
+                                   "flops_per_lu": FP32_FLOPS_PER_LU_LOCAL})
+        # VALU issue: the kernel's measured VALU lane instructions per lattice
+        # update (committed counter summary) at the achieved update rate
         ipl = _summary_value(LOCAL_VALU_SUMMARY,
                              name + r" VALU lane instructions per lattice update:\s*([0-9.]+)",
                              LOCAL_KERNEL_SRC)
         if ipl is not None:
-            bound = VALU_ISSUE_PER_S * 64 / ipl / 1e6
-            out[name].update(valu_lane_instructions_per_lu=ipl, onchip_valu_bound_mlups=round(bound),
-                             frac_of_onchip_bound=round(lu / best / 1e6 / bound, 4))
+            out[name]["roofline"].update(
+                valu_lane_instructions_per_lu=ipl,
+                valu_issue_frac=round(lu / med * ipl / 64 / VALU_ISSUE_PER_S, 4))
         if name == "tiles32":
             keff_tiles = r.keff.reshape(n // 32, n // 32, 4)
     return out, keff_tiles
+
+
+def cpu_baseline_local(kappa, sample_every_tile=16, sample_every_mixed=32, single=8):
+    """The oracle's local problems (Sec. 3, Eq. tensor-kappa: both drives to
+    a relative change of 1e-7 per 100 steps, as the GPU runs them) on a
+    bounded sample of the same two sets: every `sample_every_tile`-th tile and
+    every `sample_every_mixed`-th mixed patch, items spread over host threads
+    (one oracle call per thread at a time, each single-threaded), plus the
+    first `single` tiles on one thread."""
+    import concurrent.futures as cf
+    from oracle import oracle as O
+    from paper_1312_0195_amd import inputs as I
+    n = kappa.shape[0]
+    sets = {"tiles32": I.tile_patches(n, n, 32), "mixed": I.mixed_patches(4096, n, n, seed=1)}
+    threads = min(os.cpu_count() or 1, 16)
+
+    def solve(args):
+        O.set_threads(1)
+        x0, y0, sd = args
+        return O.local_keff(I.cut_patch(kappa, x0, y0, sd), 0.8, 0.4, 0.1, 1e-6,
+                            check_every=100, tol=1e-7, max_steps=400000)
+
+    out = {"cores": threads, "kind": "oracle", "cpu_model": _cpu_model()}
+    O.lib()
+    for name, (x0, y0, side) in sets.items():
+        every = sample_every_tile if name == "tiles32" else sample_every_mixed
+        idx = np.arange(0, len(x0), every)
+        work = [(int(x0[i]), int(y0[i]), int(side[i])) for i in idx]
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            res = list(ex.map(solve, work))
+        dt = time.perf_counter() - t0
+        lu = sum(float(r.steps.sum()) * w[2] ** 2 for r, w in zip(res, work))
+        out[name] = dict(value=round(len(work) / dt, 2), unit="patches/s",
+                         sample=f"{len(work)} of {len(x0)} patches (every {every}-th), {dt:.1f} s",
+                         mlups=round(lu / dt / 1e6, 1))
+    x0, y0, side = sets["tiles32"]
+    main_threads = O.num_threads()
+    t0 = time.perf_counter()
+    res = [solve((int(x0[i]), int(y0[i]), int(side[i]))) for i in range(single)]
+    dt = time.perf_counter() - t0
+    O.set_threads(main_threads)  # solve() set this thread's OpenMP team to one
+    out["tiles32_single_thread"] = dict(value=round(single / dt, 2), unit="patches/s",
+                                        sample=f"the first {single} tiles, one thread, {dt:.1f} s")
+    return out
 
 
 def bench_coarse(L, torch, keff, r=32, reps=3):
@@ -313,6 +392,32 @@ def bench_d3q19(L, torch, n=256, steps=200, warmup=20):
                     D3Q19_BYTES_PER_LU * cells / (us * 1e-6) / 1e9 / copy_gbs, 4))
 
 
+def bench_seeds(L, torch, steps, no_local, seeds=(2, 3)):
+    """The fine step and the local problems on the same workloads drawn with
+    other seeds (the headline numbers use seed 1): fine MLUPS over `steps`
+    steps (median of 3) and local patches/s (median of 3 calls)."""
+    from paper_1312_0195_amd import inputs as I
+    out = {}
+    for seed in seeds:
+        kappa = I.workload_fine(seed=seed)["kappa"]
+        n = kappa.shape[0]
+        f = bench_fine(L, torch, kappa, steps, 200, repeats=3)
+        o = dict(fine_mlups_median=round(float(np.median(
+            [n * n * steps / (ms * 1e-3) / 1e6 for ms in f["run_ms"]])), 1),
+            fine_steps=steps, fine_step_kernel_us=round(f["step_kernel_ms"] * 1e3, 2))
+        if not no_local:
+            kd = torch.as_tensor(kappa).cuda()
+            sets = {"tiles32": I.tile_patches(n, n, 32),
+                    "mixed": I.mixed_patches(4096, n, n, seed=seed)}
+            loc, _ = bench_local(L, torch, kd, reps=3, sets=sets)
+            for k, v in loc.items():
+                o[k + "_patches_per_s_median"] = round(v["patches_per_s"], 1)
+                o[k + "_mean_steps"] = round(v["mean_steps"], 1)
+            del kd
+        out[f"seed{seed}"] = o
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -356,6 +461,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-local", action="store_true")
     ap.add_argument("--no-d3q19", action="store_true")
+    ap.add_argument("--no-seeds", action="store_true", help="skip the seed 2 and 3 workloads")
     ap.add_argument("--no-paper-timing", action="store_true",
                     help="skip the 100 x 100 Sec. 4.1 leg (its 200000 steps swamp a profile)")
     ap.add_argument("--only-d3q19", action="store_true",
@@ -424,6 +530,8 @@ def main():
                      "traffic": traffic,
                      "kernel": f"k_stepd<float, walls, scalar, {DEPTH}> ({DEPTH} time steps per launch)",
                      "avg_launch_us": round(step_ms * 1e3, 3),
+                     "launches_timed": KERNEL_LAUNCHES,
+                     "warmup_launches": KERNEL_WARMUP_LAUNCHES,
                      "flops_per_launch": FLOPS_PER_LU * DEPTH * cells,
                      "lattice_updates_per_launch": DEPTH * cells,
                      "hbm_bytes_per_launch_algorithmic": BYTES_PER_LU * cells,
@@ -433,7 +541,9 @@ def main():
                      round(valu / (t_launch * VALU_ISSUE_PER_S), 4),
                      "single_step_hbm_equivalent_gbs": round(mlups * 1e6 * BYTES_PER_LU / 1e9, 1)},
         "wall_s": round(fine["wall_s"], 3),
+        "mlups_runs": [round(cells * args.steps / (ms * 1e-3) / 1e6, 1) for ms in fine["run_ms"]],
     }
+    result["mlups_median"] = float(np.median(result["mlups_runs"]))
     result["step_forms"] = bench_forms(L, torch, kappa)
     if not args.no_paper_timing:
         result["paper_sec41_timing"] = bench_paper_sec41(L, torch)
@@ -441,6 +551,11 @@ def main():
         kd = torch.as_tensor(kappa).cuda()
         result["local_keff"], keff_tiles = bench_local(L, torch, kd)
         result["coarse"] = bench_coarse(L, torch, keff_tiles)
+        del kd
+        if not args.no_cpu:
+            result["local_keff"]["cpu_baseline"] = cpu_baseline_local(kappa)
+    if not args.no_seeds:
+        result["seeds"] = bench_seeds(L, torch, min(args.steps, 6000), args.no_local)
     if not args.no_surrogate and not args.no_local:
         result["keff_surrogate"] = bench_surrogate()
     if not args.no_d3q19:
