@@ -324,6 +324,21 @@ lbm_status lbm_cnn_forward_limited(const float *d_params, int32_t batch, const f
                                    float *d_pred, float *d_stats, int32_t max_workgroups, void *d_ws,
                                    size_t ws_bytes, hipStream_t stream);
 
+/* lbm_cnn_forward_limited without a workspace argument, for callers that
+ * cannot allocate device memory during a run (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). The call allocates
+ * nothing: the packed weights and the patch counter live in a static device
+ * array of the library (128 KB per device, reserved for the life of the
+ * process); the first call on a device looks up its address. Inputs and
+ * outputs are as in lbm_cnn_forward_limited; results are bit-identical to it.
+ * Every call on one device shares that array, so calls that overlap on one
+ * device (other streams, other host threads) race and must be serialised by
+ * the caller; each call clears what it needs at its start. A call whose
+ * scratch would exceed the reserved size returns LBM_EINVAL (the inference
+ * scratch does not depend on the batch, so none does today). Asynchronous. */
+lbm_status lbm_cnn_forward_noalloc(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
+                                   float *d_pred, float *d_stats, int32_t max_workgroups, hipStream_t stream);
+
 /* Loss = mean over the batch and both outputs of (prediction - target)^2,
  * d_target FP32 [batch][2] (log kxx, log kyy of the untransformed patch).
  * d_sym: int8 [batch] symmetry code applied to each patch (training-time

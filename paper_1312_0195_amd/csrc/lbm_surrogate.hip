@@ -41,9 +41,18 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "lbm_internal.h"
+
+// Scratch of lbm_cnn_forward_noalloc: what the inference workspace holds
+// (the BF16 conv weights in both operand layouts and the patch counter), one
+// copy per device, kept until the process ends. Host code never uses this
+// name as an address: it takes the device address once per device with
+// hipGetSymbolAddress and passes that to the kernels.
+constexpr size_t kNoAllocScratchBytes = 128 * 1024;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace lbm {
 namespace {
@@ -914,6 +923,53 @@ extern "C" lbm_status lbm_cnn_forward_limited(const float *d_params, int32_t bat
     if (s != LBM_OK) return s;
     char *ws = static_cast<char *>(d_ws);
     s = pack(d_params, ws, L, stream);
+    if (s != LBM_OK) return s;
+    return forward(d_params, batch, d_logk, nullptr, n_sym, d_pred, d_stats, ws, L, false, stream,
+                   max_workgroups);
+}
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device (with it current) and kept.
+lbm_status scratch_address(void **out)
+{
+    int dev = -1;
+    LBM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(LBM_EDEVICE, "lbm_cnn_forward_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_check(e, "lbm_cnn_forward_noalloc: hipGetSymbolAddress(scratch)");
+        if (!p) return set_error(LBM_EDEVICE, "lbm_cnn_forward_noalloc: scratch has no device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+
+extern "C" lbm_status lbm_cnn_forward_noalloc(const float *d_params, int32_t batch, const float *d_logk,
+                                              int32_t n_sym, float *d_pred, float *d_stats,
+                                              int32_t max_workgroups, hipStream_t stream)
+{
+    if (batch < 1 || !d_params || !d_logk || !d_pred)
+        return set_error(LBM_EINVAL, "lbm_cnn_forward_noalloc: batch < 1 or NULL argument");
+    if (n_sym < 1 || n_sym > 8) return set_error(LBM_EINVAL, "lbm_cnn_forward_noalloc: n_sym must lie in [1, 8]");
+    if (max_workgroups < 0) return set_error(LBM_EINVAL, "lbm_cnn_forward_noalloc: max_workgroups must be >= 0");
+    const SurLayout L = sur_layout(batch, false);
+    if (L.total > kNoAllocScratchBytes)
+        return set_error(LBM_EINVAL, "lbm_cnn_forward_noalloc: the call needs " + std::to_string(L.total) +
+                                         " bytes of scratch, more than the " +
+                                         std::to_string(kNoAllocScratchBytes) + " reserved");
+    void *p = nullptr;
+    lbm_status s = scratch_address(&p);
+    if (s != LBM_OK) return s;
+    char *ws = static_cast<char *>(p);
+    s = pack(d_params, ws, L, stream);  // also zeroes the patch counter
     if (s != LBM_OK) return s;
     return forward(d_params, batch, d_logk, nullptr, n_sym, d_pred, d_stats, ws, L, false, stream,
                    max_workgroups);

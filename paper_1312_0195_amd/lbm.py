@@ -32,6 +32,7 @@ EXPORTS = (
     "lbm_coarse_workspace_bytes", "lbm_coarse_solve", "lbm_block_average", "lbm_status_str",
     "lbm_last_error",
     "lbm_cnn_param_count", "lbm_cnn_workspace_bytes", "lbm_cnn_forward", "lbm_cnn_forward_limited",
+    "lbm_cnn_forward_noalloc",
     "lbm_cnn_gradients",
     "lbm_cnn_train_step", "lbm_patch_stats",
     "lbm3d_workspace_bytes", "lbm3d_init", "lbm3d_step", "lbm3d_fields", "lbm3d_get_populations",
@@ -158,6 +159,9 @@ def lib():
     L.lbm_cnn_forward_limited.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
                                           _vp, ctypes.c_size_t, _vp]
     L.lbm_cnn_forward_limited.restype = ctypes.c_int
+    L.lbm_cnn_forward_noalloc.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
+                                          _vp]
+    L.lbm_cnn_forward_noalloc.restype = ctypes.c_int
     L.lbm_cnn_gradients.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp]
     L.lbm_cnn_gradients.restype = ctypes.c_int
@@ -375,6 +379,13 @@ def lbm_cnn_forward_limited(d_params, batch, d_logk, n_sym, d_pred, d_stats, max
     _raise(lib().lbm_cnn_forward_limited(_ptr(d_params), int(batch), _ptr(d_logk), int(n_sym),
                                          _ptr(d_pred), _ptr(d_stats), int(max_workgroups), _ptr(d_ws),
                                          int(ws_bytes), _stream(stream)), "lbm_cnn_forward_limited")
+
+
+def lbm_cnn_forward_noalloc(d_params, batch, d_logk, n_sym, d_pred, d_stats, max_workgroups=0,
+                            stream=None) -> None:
+    _raise(lib().lbm_cnn_forward_noalloc(_ptr(d_params), int(batch), _ptr(d_logk), int(n_sym),
+                                         _ptr(d_pred), _ptr(d_stats), int(max_workgroups),
+                                         _stream(stream)), "lbm_cnn_forward_noalloc")
 
 
 def lbm_cnn_gradients(d_params, batch, d_logk, d_sym, d_target, d_grad, d_loss, d_pred, d_ws,
