@@ -46,8 +46,12 @@ typedef enum {
 
 /* Population storage of the fine-grid solver. */
 enum {
-    LBM_F32_SHIFTED = 0, /* FP32 deviations f_a - w_a rho0 (the fast path) */
-    LBM_F64 = 1          /* FP64 deviations (reference-precision runs) */
+    LBM_F32_SHIFTED = 0, /* FP32 deviations f_a - w_a rho0, FP64 collision arithmetic */
+    LBM_F64 = 1,         /* FP64 deviations (reference-precision runs) */
+    LBM_F32_FAST = 2     /* fine solver only: FP32 deviations and FP32 collision
+                            arithmetic, with the drag entering as its deficit
+                            1 - D so that it keeps its relative precision
+                            (Shan-Chen form only) */
 };
 
 /* Form of the time step. Both give the same populations up to rounding (with
@@ -166,6 +170,19 @@ typedef struct {
     int32_t schedule;     /* order in which the items of one side start:
                              LBM_SCHEDULE_GIVEN or LBM_SCHEDULE_COST. Results
                              do not depend on it, only the run time. */
+    int32_t fp32_step_budget; /* FP32 state only (0: no budget). The FP32 state
+                             is stored rebased on the item's mean momentum, so
+                             a slowly relaxing but nearly uniform flow keeps
+                             its precision; in a patch with nearly blocked
+                             directions the non-uniform part dominates, and a
+                             converged FP32 state can stop short of the fixed
+                             point by a few 1e-4 of a blocked direction's own
+                             small K_eff. An item that has not converged after
+                             this many steps (rounded up to a check) is
+                             stopped and run again from rest with FP64 state
+                             (a second launch on `stream`; sides up to 45),
+                             which reports its own steps and flag. Larger
+                             sides finish in FP32 and get flag 3. */
 } lbm_local_params;
 
 /* Start order of the local problems. An item's step count varies by orders
@@ -205,7 +222,8 @@ size_t lbm_local_workspace_bytes(int32_t n_patches);
  *          skipped drive are NaN).
  * d_steps: device int32 [n_patches][2] steps taken per drive (or NULL).
  * d_flags: device int32 [n_patches][2]: 0 converged, 1 step cap reached,
- *          2 non-finite, -1 drive skipped (or NULL).
+ *          2 non-finite, 3 converged in FP32 state past fp32_step_budget
+ *          (side too large for the FP64 re-run), -1 drive skipped (or NULL).
  * tiles/n_tiles: optional tile table (NULL/0 for the built-in one).
  * block_threads: workgroup size, 256, 512 or 1024 (0 for 1024); FP64 items
  *          run with at most 512 (tile rows asking for more are ignored), so
@@ -323,6 +341,18 @@ lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_
 lbm_status lbm_cnn_forward_limited(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
                                    float *d_pred, float *d_stats, int32_t max_workgroups, void *d_ws,
                                    size_t ws_bytes, hipStream_t stream);
+
+/* lbm_cnn_forward_limited with, in place of the statistics, the spread of
+ * the symmetric predictions: d_spread FP32 [batch][2] gets, for log kxx and
+ * log kyy, the largest minus the smallest of the n_sym predictions whose mean
+ * is d_pred (0 for n_sym = 1). The symmetries of the square map a patch's
+ * K_eff tensor exactly onto that of the transformed patch, so their
+ * disagreement measures how far the network is from the map it learned;
+ * the surrogate path sends patches with a large spread to the LBM.
+ * d_pred and d_spread must not be NULL. Asynchronous. */
+lbm_status lbm_cnn_forward_spread(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,
+                                  float *d_pred, float *d_spread, int32_t max_workgroups, void *d_ws,
+                                  size_t ws_bytes, hipStream_t stream);
 
 /* lbm_cnn_forward_limited without a workspace argument, for callers that
  * cannot allocate device memory during a run (code under HIP graph capture,

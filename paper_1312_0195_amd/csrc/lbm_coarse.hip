@@ -34,7 +34,8 @@ constexpr int kCPT64 = 2;  // cells per thread, FP64 populations (2048 cells)
 template <typename R>
 struct CoarseArgs {
     int nx, ny;
-    const R *__restrict__ M;         // [4][N] per-cell matrix (m00, m01, m10, m11)
+    const R *__restrict__ M;         // [4][N] per-cell drag deficit E = I - M (e00, e01, e10, e11),
+                                     // M = (K + h I)^{-1} K; E keeps its relative precision in FP32
     const R *__restrict__ heg;       // [2][N] eps G_c / 2 per cell
     double om, omc, twotau, omtt;
     double tol;
@@ -68,12 +69,14 @@ __global__ void k_coarse_coef(const double *__restrict__ keff, const double *__r
     const double adet = axx * ayy - kxy * kyx;
     if (!(std::isfinite(det) && det > 0.0 && std::isfinite(adet) && adet != 0.0 && kxx > 0.0 && kyy > 0.0))
         atomicOr(bad, 1);
-    const double ia = 1.0 / adet;
+    // E = I - M = h (K + h I)^{-1}: rounded to FP32, M itself would lose the
+    // relative precision of the drag I - M of permeable cells
+    const double ia = h / adet;
     const int N = n;
-    M[c] = (R)(ia * (ayy * kxx - kxy * kyx));
-    M[N + c] = (R)(ia * (ayy * kxy - kxy * kyy));
-    M[2 * N + c] = (R)(ia * (-kyx * kxx + axx * kyx));
-    M[3 * N + c] = (R)(ia * (-kyx * kxy + axx * kyy));
+    M[c] = (R)(ia * ayy);
+    M[N + c] = (R)(-ia * kxy);
+    M[2 * N + c] = (R)(-ia * kyx);
+    M[3 * N + c] = (R)(ia * axx);
     const double gx = r * (force ? force[2 * c] : gxf), gy = r * (force ? force[2 * c + 1] : gyf);
     heg[c] = (R)(0.5 * eps * gx);
     heg[N + c] = (R)(0.5 * eps * gy);
@@ -96,8 +99,9 @@ __device__ __forceinline__ void collide_t(double f[9], const R m[4], R hx0, R hy
     const double jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
     const double rho = 1.0 + dr;
     const double hx = jx + (double)hx0 * rho, hy = jy + (double)hy0 * rho;
-    const double mx = a.twotau * ((double)m[0] * hx + (double)m[1] * hy) + a.omtt * jx;
-    const double my = a.twotau * ((double)m[2] * hx + (double)m[3] * hy) + a.omtt * jy;
+    // M h = h - E h
+    const double mx = a.twotau * ((hx - (double)m[0] * hx) - (double)m[1] * hy) + a.omtt * jx;
+    const double my = a.twotau * ((hy - (double)m[3] * hy) - (double)m[2] * hx) + a.omtt * jy;
     const double om = a.om, omc = a.omc;
     const double s0 = (4.0 / 9.0) * om * dr;
     const double b = (1.0 / 9.0) * om * dr;
@@ -128,8 +132,8 @@ __device__ __forceinline__ void cell_velocity(const double fd[9], const R m[4], 
     const double jy = (fd[2] - fd[4]) + ((fd[5] + fd[6]) - (fd[7] + fd[8]));
     rho = 1.0 + dr;
     const double hx = jx + (double)hx0 * rho, hy = jy + (double)hy0 * rho;
-    ux = ((double)m[0] * hx + (double)m[1] * hy) / rho;
-    uy = ((double)m[2] * hx + (double)m[3] * hy) / rho;
+    ux = ((hx - (double)m[0] * hx) - (double)m[1] * hy) / rho;
+    uy = ((hy - (double)m[3] * hy) - (double)m[2] * hx) / rho;
 }
 
 // One workgroup runs the whole periodic coarse lattice to steady state.

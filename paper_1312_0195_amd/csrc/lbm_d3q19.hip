@@ -61,7 +61,9 @@ template <typename R>
 struct Args3 {
     const R *__restrict__ fin;
     R *__restrict__ fout;
-    const R *__restrict__ coef;  // D = 1 / (1 + eps nu / (2 kappa)) per cell
+    const R *__restrict__ coef;  // drag deficit E = 1 - D = h / (kappa + h), h = eps nu / 2, per cell
+                                 // (D = 1 / (1 + h / kappa) itself would lose the relative
+                                 // precision of 1 - D in FP32 for permeable cells)
     int nx, ny, nz;
     size_t stride;               // elements per population plane
     double hegx, hegy, hegz;     // eps G / 2
@@ -163,13 +165,14 @@ __device__ __forceinline__ void moments3(const double f[Q], double &dr, double &
 
 // Post-collision deviations in place: rho u_eq = 2 tau D (j + rho eps G / 2)
 // + (1 - 2 tau) j and f~_a <- (1 - 1/tau) f~_a + (w_a / tau)(dr + 3 e_a . rho u_eq).
+// E: the cell's drag deficit 1 - D as stored (full relative precision in FP32).
 template <typename R>
-__device__ __forceinline__ void collide3(const Args3<R> &a, double f[Q], double D)
+__device__ __forceinline__ void collide3(const Args3<R> &a, double f[Q], double E)
 {
     double dr, jx, jy, jz;
     moments3(f, dr, jx, jy, jz);
     const double rho = a.rho0 + dr;
-    const double tD = a.twotau * D;
+    const double tD = a.twotau - a.twotau * E;
     const double mx = tD * (jx + a.hegx * rho) + a.omtt * jx;
     const double my = tD * (jy + a.hegy * rho) + a.omtt * jy;
     const double mz = tD * (jz + a.hegz * rho) + a.omtt * jz;
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(kBlock3) void k3_fields(Args3<R> a, double *__restr
         moments3(f, dr, jx, jy, jz);
         const double rho = a.rho0 + dr;
         const size_t c = ((size_t)z * a.ny + y) * a.nx + x;
-        const double D = (double)a.coef[c];
+        const double D = 1.0 - (double)a.coef[c];
         ux = D * (jx + a.hegx * rho) / rho;
         uy = D * (jy + a.hegy * rho) / rho;
         uz = D * (jz + a.hegz * rho) / rho;
@@ -508,8 +511,8 @@ __global__ __launch_bounds__(256) void k3_init(const double *__restrict__ kappa,
     const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (c >= n) return;
     const double k = kappa[c];
-    if (!(k > 0.0)) atomicOr(bad, 1);  // also NaN; +inf gives D = 1 (no drag)
-    coef[c] = (R)(1.0 / (1.0 + h / k));
+    if (!(k > 0.0)) atomicOr(bad, 1);  // also NaN; +inf gives E = 0 (no drag)
+    coef[c] = (R)(h / (k + h));         // E = 1 - D, D = 1 / (1 + h / kappa)
 #pragma unroll
     for (int q = 0; q < Q; ++q) pops[(size_t)q * stride + c] = (R)0;
 }

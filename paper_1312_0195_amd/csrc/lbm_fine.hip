@@ -24,7 +24,11 @@
 // with D = 1 / (1 + eps nu / (2 kappa)) per cell, or, for a tensor
 // permeability K, rho u = (K + eps nu I / 2)^{-1} K (j + eps rho G / 2) (Eq.
 // u-of-S-C with Eq. f_m-depends-on-u-and-tensor-k). No division is needed in
-// the step. The algebra is exact; only the rounding order differs from a
+// the step. The coefficient planes hold the drag deficit E = 1 - D =
+// h / (kappa + h), h = eps nu / 2 (tensor: I - M = h (K + h I)^{-1}), not D:
+// rounded to FP32, D would lose the relative precision of the drag 1 - D in
+// permeable cells (its absolute rounding error 2^-25 is 2e-4 of 1 - D at
+// kappa = 130, eps nu = 0.04), E keeps it; D = 1 - E is formed in FP64. The algebra is exact; only the rounding order differs from a
 // literal transcription. The collision arithmetic is FP64 for both storage
 // types; FP32 storage only rounds the nine values written per cell.
 #include <hip/hip_runtime.h>
@@ -60,6 +64,23 @@ struct StepArgs {
     R rho0;
     // FP64 copies of the constants for the FP64 arithmetic
     double hegx_d, hegy_d, om_d, omc_d, twotau_d, omtt_d, rho0_d;
+};
+
+// The relaxation constants in the arithmetic type A of a collision: FP64
+// arithmetic uses the FP64 copies, FP32 arithmetic the storage-type ones.
+template <typename A, typename R>
+struct Kc {
+    A om, omc, twotau, omtt, hegx, hegy, rho0;
+    __device__ explicit Kc(const StepArgs<R> &a)
+    {
+        if constexpr (sizeof(A) == 8) {
+            om = a.om_d; omc = a.omc_d; twotau = a.twotau_d; omtt = a.omtt_d;
+            hegx = a.hegx_d; hegy = a.hegy_d; rho0 = a.rho0_d;
+        } else {
+            om = (A)a.om; omc = (A)a.omc; twotau = (A)a.twotau; omtt = (A)a.omtt;
+            hegx = (A)a.hegx; hegy = (A)a.hegy; rho0 = (A)a.rho0;
+        }
+    }
 };
 
 // Plane accessors: element i of plane q of an SoA array with a plane stride.
@@ -256,48 +277,67 @@ struct LdsCoef {
     __device__ R ld(int, int i) const { return p[i]; }
 };
 
-// PK: 1 scalar drag coefficient D, 4 tensor M (Shan-Chen form); 0 the Guo
+// PK: 1 scalar drag deficit E = 1 - D, 4 tensor I - M (Shan-Chen form); 0 the Guo
 // form with coef = eps nu / kappa. Coefficients come from cm at index c, the
 // per-cell force from fm at index cf.
-template <typename R, int PK, bool FF, class CM, class FM>
-__device__ __forceinline__ void collide_m(const StepArgs<R> &a, double f[9], int c, int cf, const CM &cm,
+template <typename R, int PK, bool FF, class CM, class FM, typename A>
+__device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, int cf, const CM &cm,
                                           const FM &fm)
 {
-    if (PK == 0) {
+    if constexpr (PK == 0) {
+        static_assert(sizeof(A) == 8, "the Guo form runs in FP64 arithmetic");
         collide_guo<R, FF>(a, f, c, cf, cm, fm);
         return;
-    }
-    double dr, jx, jy;
+    } else {
+    const Kc<A, R> k(a);
+    A dr, jx, jy;
     moments(f, dr, jx, jy);
-    const double rho = a.rho0_d + dr;
-    double hx, hy;
+    const A rho = k.rho0 + dr;
+    A gx, gy;  // eps rho G / 2
     if (FF) {
-        hx = jx + (double)fm.ld(0, cf) * rho;
-        hy = jy + (double)fm.ld(1, cf) * rho;
+        gx = (A)fm.ld(0, cf) * rho;
+        gy = (A)fm.ld(1, cf) * rho;
     } else {
-        hx = jx + a.hegx_d * rho;
-        hy = jy + a.hegy_d * rho;
+        gx = k.hegx * rho;
+        gy = k.hegy * rho;
     }
-    double mx, my;  // rho u_eq
-    if (PK == 1) {
-        const double tD = a.twotau_d * (double)cm.ld(0, c);
-        mx = tD * hx + a.omtt_d * jx;
-        my = tD * hy + a.omtt_d * jy;
+    const A hx = jx + gx, hy = jy + gy;
+    A mx, my;  // rho u_eq = 2 tau M h + (1 - 2 tau) j with M = I - E
+    if constexpr (sizeof(A) == 8) {
+        // FP64: M = I - E formed exactly enough, then the product
+        if (PK == 1) {
+            const A tD = k.twotau - k.twotau * (A)cm.ld(0, c);
+            mx = tD * hx + k.omtt * jx;
+            my = tD * hy + k.omtt * jy;
+        } else {
+            const A e00 = cm.ld(0, c), e01 = cm.ld(1, c);
+            const A e10 = cm.ld(2, c), e11 = cm.ld(3, c);
+            mx = k.twotau * ((hx - e00 * hx) - e01 * hy) + k.omtt * jx;
+            my = k.twotau * ((hy - e11 * hy) - e10 * hx) + k.omtt * jy;
+        }
     } else {
-        const double m00 = cm.ld(0, c), m01 = cm.ld(1, c);
-        const double m10 = cm.ld(2, c), m11 = cm.ld(3, c);
-        mx = a.twotau_d * (m00 * hx + m01 * hy) + a.omtt_d * jx;
-        my = a.twotau_d * (m10 * hx + m11 * hy) + a.omtt_d * jy;
+        // FP32: = j + 2 tau eps rho G / 2 - 2 tau E h, so the drag enters as
+        // the small correction 2 tau E h and keeps its relative precision
+        if (PK == 1) {
+            const A tE = k.twotau * (A)cm.ld(0, c);
+            mx = (jx + k.twotau * gx) - tE * hx;
+            my = (jy + k.twotau * gy) - tE * hy;
+        } else {
+            const A e00 = cm.ld(0, c), e01 = cm.ld(1, c);
+            const A e10 = cm.ld(2, c), e11 = cm.ld(3, c);
+            mx = (jx + k.twotau * gx) - k.twotau * (e00 * hx + e01 * hy);
+            my = (jy + k.twotau * gy) - k.twotau * (e10 * hx + e11 * hy);
+        }
     }
-    const double om = a.om_d, omc = a.omc_d;
-    const double s0 = (4.0 / 9.0) * om * dr;
-    const double b = (1.0 / 9.0) * om * dr;
-    const double bx = (1.0 / 3.0) * om * mx;
-    const double by = (1.0 / 3.0) * om * my;
-    const double cc = (1.0 / 36.0) * om * dr;
-    const double cx = (1.0 / 12.0) * om * mx;
-    const double cy = (1.0 / 12.0) * om * my;
-    const double pp = cx + cy, qq = cx - cy;
+    const A om = k.om, omc = k.omc;
+    const A s0 = (A)(4.0 / 9.0) * om * dr;
+    const A b = (A)(1.0 / 9.0) * om * dr;
+    const A bx = (A)(1.0 / 3.0) * om * mx;
+    const A by = (A)(1.0 / 3.0) * om * my;
+    const A cc = (A)(1.0 / 36.0) * om * dr;
+    const A cx = (A)(1.0 / 12.0) * om * mx;
+    const A cy = (A)(1.0 / 12.0) * om * my;
+    const A pp = cx + cy, qq = cx - cy;
     f[0] = omc * f[0] + s0;
     f[1] = omc * f[1] + (b + bx);
     f[2] = omc * f[2] + (b + by);
@@ -307,19 +347,20 @@ __device__ __forceinline__ void collide_m(const StepArgs<R> &a, double f[9], int
     f[6] = omc * f[6] + (cc - qq);
     f[7] = omc * f[7] + (cc - pp);
     f[8] = omc * f[8] + (cc + qq);
+    }
 }
 
 // Collision of lattice cell c with coefficients and force read through plane
 // accessors of type M.
-template <typename R, int PK, bool FF, class M = GMem<R>>
-__device__ __forceinline__ void collide_cell(const StepArgs<R> &a, double f[9], int c)
+template <typename R, int PK, bool FF, class M = GMem<R>, typename A>
+__device__ __forceinline__ void collide_cell(const StepArgs<R> &a, A f[9], int c)
 {
     const M cm{a.coef, nullptr, a.cstride}, fm{a.hforce, nullptr, a.cstride};
     collide_m<R, PK, FF>(a, f, c, c, cm, fm);
 }
 
 // One time step per launch: pull, collide, store (one HBM pass).
-template <typename R, bool WALLS, int PK, bool FF>
+template <typename R, bool WALLS, int PK, bool FF, typename A = double>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
 {
     const int bid = xcd_block(blockIdx.x, gridDim.x);
@@ -330,12 +371,11 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<R> a)
     R fr[9];
     pull<R, WALLS>(a.fin, a.stride, a.nx, a.ny, x, y, fr);
     const int c = y * a.nx + x;
-    // The arithmetic runs in FP64 whatever the storage type: with FP32 storage
-    // the rounding of the collision itself (not of the stored values) is what
-    // limits accuracy, and FP64 VALU work is hidden under the HBM traffic.
-    double f[9];
+    // The arithmetic runs in FP64 whatever the storage type (LBM_F32_SHIFTED,
+    // LBM_F64), or in FP32 with FP32 storage (LBM_F32_FAST).
+    A f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = (double)fr[i];
+    for (int i = 0; i < 9; ++i) f[i] = (A)fr[i];
     collide_cell<R, PK, FF>(a, f, c);
     R *o = a.fout;
     const size_t S = (size_t)a.stride;
@@ -381,7 +421,7 @@ template <> struct TileD<double, LBM_DEEP> : TileShape<LBM_TILE6D> {};
 // one-step launches while HBM sees one read and one write of the state per D
 // steps (plus the halo, which neighbouring tiles mostly find in L2). Loads and
 // stores go through BMem (32-bit offsets, plane bases in scalar registers).
-template <typename R, bool WALLS, int PK, bool FF, int D>
+template <typename R, bool WALLS, int PK, bool FF, int D, typename A = double>
 __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
 {
     constexpr int TX = TileD<R, D>::TX, TY = TileD<R, D>::TY, BS = TileD<R, D>::BS;
@@ -427,17 +467,17 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
         return true;
     };
     // the nine pre-collision values of P cell c (lattice row y) from the buffer
-    auto pull_lds = [&](int c, int y, bool edge, double f[9]) {
+    auto pull_lds = [&](int c, int y, bool edge, A f[9]) {
         const bool lo = WALLS && edge && y == 0, hi = WALLS && edge && y == ny - 1;
-        f[0] = (double)P[0][c];
-        f[1] = (double)P[1][c - 1];
-        f[3] = (double)P[3][c + 1];
-        f[2] = (double)(lo ? P[4][c] : P[2][c - AX]);
-        f[5] = (double)(lo ? P[7][c] : P[5][c - AX - 1]);
-        f[6] = (double)(lo ? P[8][c] : P[6][c - AX + 1]);
-        f[4] = (double)(hi ? P[2][c] : P[4][c + AX]);
-        f[7] = (double)(hi ? P[5][c] : P[7][c + AX + 1]);
-        f[8] = (double)(hi ? P[6][c] : P[8][c + AX - 1]);
+        f[0] = (A)P[0][c];
+        f[1] = (A)P[1][c - 1];
+        f[3] = (A)P[3][c + 1];
+        f[2] = (A)(lo ? P[4][c] : P[2][c - AX]);
+        f[5] = (A)(lo ? P[7][c] : P[5][c - AX - 1]);
+        f[6] = (A)(lo ? P[8][c] : P[6][c - AX + 1]);
+        f[4] = (A)(hi ? P[2][c] : P[4][c + AX]);
+        f[7] = (A)(hi ? P[5][c] : P[7][c + AX + 1]);
+        f[8] = (A)(hi ? P[6][c] : P[8][c + AX - 1]);
     };
     const int w1 = tw + 2 * H, h1 = th + 2 * H;
     auto body = [&](auto fast_tag) {
@@ -464,9 +504,9 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
                 if (px >= w1 || py >= h1 || !cell_of(px, py, x, y)) continue;
                 pullm<R, WALLS>(mem, nx, ny, x, y, fr);
             }
-            double f[9];
+            A f[9];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) f[q] = (double)fr[q];
+            for (int q = 0; q < 9; ++q) f[q] = (A)fr[q];
             if constexpr (CL) {
                 const R d = BMem<R>{a.coef, nullptr, a.cstride}.ld(0, y * nx + x);
                 Dl[i] = d;
@@ -493,7 +533,7 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
                 const bool in = FAST ? i < RN
                                      : (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y));
                 if (in) {
-                    double f[9];
+                    A f[9];
                     pull_lds(py * AX + px, y, !FAST, f);
 #pragma unroll
                     for (int q = 0; q < 9; ++q) pr[k][q] = (R)f[q];
@@ -508,9 +548,9 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
                 const bool in = FAST ? i < RN
                                      : (i < RN && px < w1 - ph && py < h1 - ph && cell_of(px, py, x, y));
                 if (in) {
-                    double f[9];
+                    A f[9];
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) f[q] = (double)pr[k][q];
+                    for (int q = 0; q < 9; ++q) f[q] = (A)pr[k][q];
                     const int c = py * AX + px;
                     if constexpr (CL)
                         collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
@@ -527,7 +567,7 @@ __global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
             const int lx = i % TX, ly = i / TX;
             if (!FAST && (lx >= tw || ly >= th)) continue;
             const int x = x0 + lx, y = y0 + ly;
-            double f[9];
+            A f[9];
             const int c = (ly + H) * AX + (lx + H);
             pull_lds(c, y, !FAST, f);
             const int g = y * nx + x;
@@ -575,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(StepArgs<R> a, double *__rest
             hy = jy + a.hegy_d * rho;
         }
         if (PK == 1) {
-            const double D = (double)a.coef[c];
+            const double D = 1.0 - (double)a.coef[c];
             ux = D * hx / rho;
             uy = D * hy / rho;
         } else if (PK == 0) {
@@ -583,10 +623,10 @@ __global__ __launch_bounds__(kBlock) void k_fields(StepArgs<R> a, double *__rest
             ux = hx / den;
             uy = hy / den;
         } else {
-            const double m00 = a.coef[c], m01 = a.coef[a.cstride + c];
-            const double m10 = a.coef[2 * a.cstride + c], m11 = a.coef[3 * a.cstride + c];
-            ux = (m00 * hx + m01 * hy) / rho;
-            uy = (m10 * hx + m11 * hy) / rho;
+            const double e00 = a.coef[c], e01 = a.coef[a.cstride + c];
+            const double e10 = a.coef[2 * a.cstride + c], e11 = a.coef[3 * a.cstride + c];
+            ux = ((hx - e00 * hx) - e01 * hy) / rho;
+            uy = ((hy - e11 * hy) - e10 * hx) / rho;
         }
         if (u_out) {
             const size_t N = (size_t)a.nx * a.ny;
@@ -669,8 +709,9 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ perm
     if (PK == 1) {
         const double k = perm[c];
         if (!(k > 0.0)) atomicOr(bad, 1);  // also catches NaN
-        // D = 1 / (1 + eps nu / (2 kappa)); kappa = +inf gives 1
-        coef[c] = (R)(1.0 / (1.0 + h / k));
+        // E = 1 - D = h / (kappa + h) with D = 1 / (1 + eps nu / (2 kappa));
+        // kappa = +inf gives 0
+        coef[c] = (R)(h / (k + h));
     } else if (PK == 0) {
         const double k = perm[c];
         if (!(k > 0.0)) atomicOr(bad, 1);
@@ -684,11 +725,12 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ perm
         const double adet = axx * ayy - axy * ayx;
         const bool ok = std::isfinite(det) && det != 0.0 && std::isfinite(adet) && adet != 0.0;
         if (!ok) atomicOr(bad, 1);
-        const double ia = 1.0 / adet;
-        coef[c] = (R)(ia * (ayy * kxx - axy * kyx));
-        coef[cstride + c] = (R)(ia * (ayy * kxy - axy * kyy));
-        coef[2 * cstride + c] = (R)(ia * (-ayx * kxx + axx * kyx));
-        coef[3 * cstride + c] = (R)(ia * (-ayx * kxy + axx * kyy));
+        // E = I - M = h (K + h I)^{-1}
+        const double ia = h / adet;
+        coef[c] = (R)(ia * ayy);
+        coef[cstride + c] = (R)(-ia * axy);
+        coef[2 * cstride + c] = (R)(-ia * ayx);
+        coef[3 * cstride + c] = (R)(ia * axx);
     }
     if (force) {
         const double gx = force[2 * c], gy = force[2 * c + 1];
@@ -770,7 +812,14 @@ bool params_ok(const lbm_params *p, std::string &why)
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) { why = "rho0 must be finite and > 0"; return false; }
     if (!std::isfinite(p->gx) || !std::isfinite(p->gy)) { why = "gx, gy must be finite"; return false; }
     if (p->walls_y != 0 && p->walls_y != 1) { why = "walls_y must be 0 or 1"; return false; }
-    if (p->pop_dtype != LBM_F32_SHIFTED && p->pop_dtype != LBM_F64) { why = "unknown pop_dtype"; return false; }
+    if (p->pop_dtype != LBM_F32_SHIFTED && p->pop_dtype != LBM_F64 && p->pop_dtype != LBM_F32_FAST) {
+        why = "unknown pop_dtype";
+        return false;
+    }
+    if (p->pop_dtype == LBM_F32_FAST && p->scheme == LBM_SCHEME_GUO) {
+        why = "the Guo form runs with FP64 arithmetic only (pop_dtype LBM_F32_SHIFTED or LBM_F64)";
+        return false;
+    }
     if (p->perm_kind != LBM_PERM_SCALAR && p->perm_kind != LBM_PERM_TENSOR) { why = "perm_kind must be 1 or 4"; return false; }
     if (p->scheme != LBM_SCHEME_SHAN_CHEN && p->scheme != LBM_SCHEME_GUO) { why = "scheme must be 0 or 1"; return false; }
     if (p->scheme == LBM_SCHEME_GUO && p->perm_kind != LBM_PERM_SCALAR) { why = "the Guo form takes a scalar permeability"; return false; }
@@ -855,6 +904,12 @@ template <typename R, bool W, int PK, bool FF>
 void launch_step_t(const lbm_handle *h)
 {
     const dim3 grid(h->L.nbx * h->L.nby);
+    if constexpr (std::is_same<R, float>::value && PK != 0) {
+        if (h->p.pop_dtype == LBM_F32_FAST) {
+            hipLaunchKernelGGL((k_step<R, W, PK, FF, float>), grid, dim3(kBlock), 0, h->stream, step_args<R>(h));
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_step<R, W, PK, FF>), grid, dim3(kBlock), 0, h->stream, step_args<R>(h));
 }
 
@@ -903,6 +958,13 @@ struct StepDFn {
     {
         constexpr int TX = TileD<R, D>::TX, TY = TileD<R, D>::TY, BS = TileD<R, D>::BS;
         const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
+        if constexpr (std::is_same<R, float>::value && PK != 0) {
+            if (h->p.pop_dtype == LBM_F32_FAST) {
+                hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D, float>), dim3(ntx * nty), dim3(BS), 0, h->stream,
+                                   step_args<R>(h));
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D>), dim3(ntx * nty), dim3(BS), 0, h->stream,
                            step_args<R>(h));
     }

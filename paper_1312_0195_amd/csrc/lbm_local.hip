@@ -12,7 +12,8 @@
 //    runs one item. Items of one side share a launch-wide tile choice (G per
 //    side) and run side by side, so small patches still fill the CU.
 //  * Populations 1..8 of an item live in LDS (8 planes of side^2 FP32
-//    deviations, 32 B per cell, or FP64 with 64 B per cell); the rest
+//    values, 32 B per cell, or FP64 with 64 B per cell: deviations from the
+//    rest state moving with the item's mean momentum, see collide); the rest
 //    population and the drag coefficient stay in registers of the thread that
 //    owns the cell. FP32 items use FP32 arithmetic; FP64 items FP64 throughout,
 //    for regimes where a step changes the state by less than half an FP32 ulp
@@ -58,6 +59,7 @@ namespace {
 constexpr int kMaxSide = 64;
 constexpr int kMaxClasses = kMaxSide;  // one class per distinct side
 constexpr int kCPT = 4;                // max cells per thread
+constexpr int kEscThreads = 512;       // workgroup size of the FP64 re-run
 
 struct ClassDesc {
     int side;
@@ -65,6 +67,7 @@ struct ClassDesc {
     int nslots;        // slots in use: T / G (capped by LDS)
     int cells_per_thread;
     int begin, count;  // item range in the sorted item list
+    int esc_ok;        // FP32 items of this side may be handed to the FP64 re-run
 };
 
 struct LocalArgs {
@@ -87,9 +90,29 @@ struct LocalArgs {
     int check_every;
     int max_steps;
     int margin;                          // cells left out of the average at each side
+    // FP32 items still running after esc_steps steps stop and are queued for a
+    // re-run with FP64 state (0: never): esc_classes[c] (device table whose
+    // count the kernel increments) and esc_items (same item ranges as classes)
+    int esc_steps;
+    ClassDesc *esc_classes;
+    int4 *esc_items;
 };
 
 __device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// The reference momentum of a rebased item, rounded to 16 significant bits:
+// the mean it comes from is an FP64 sum whose rounding depends on how the
+// item's cells are spread over waves, and the coarse rounding makes the
+// reference (and so the whole FP32 state) the same for every tile layout
+// unless that sum lies within ~1e-15 of a rounding boundary. 16 bits keep the
+// stored non-uniform part within 2^-16 of the uniform flow, far below what
+// the rebasing needs.
+template <typename P>
+__device__ __forceinline__ P reference_momentum(double v)
+{
+    const unsigned b = __float_as_uint((float)v);
+    return (P)__uint_as_float((b + 0x40u) & ~0x7Fu);
+}
 
 // Relaxation constants in the arithmetic type P.
 template <typename P> struct Consts;
@@ -106,18 +129,37 @@ __device__ inline Consts<float>::Consts(const LocalArgs &a)
 __device__ inline Consts<double>::Consts(const LocalArgs &a)
     : om(a.om_d), omc(a.omc_d), twotau(a.twotau_d), omtt(a.omtt_d), heg(a.heg_d) {}
 
-// One collision of a cell in deviation form (see lbm_fine.hip for the
-// derivation): f[0..8] in, post-collision values out in f.
+// One collision of a cell, f[0..8] in, post-collision values out in f.
+//
+// The state is stored rebased: f_a = w_a rho0 + 3 w_a e_a . U + f'_a, where
+// U is a momentum uniform over the item (the mean momentum at the last
+// check, kept in the storage type) and f' is what is stored. The uniform
+// part is a rest state moving with U: streaming leaves it unchanged, and
+// since the step is linear in f (with the force entering through rho), the
+// collision of the rebased state needs U only inside the drag term. A
+// permeable patch converges slowly (relaxation time ~ kappa / (eps nu)) and
+// its flow is nearly uniform; stored as plain deviations f - w rho0, a step's
+// change to the populations falls below half an FP32 ulp of the values long
+// before the fixed point (measured: K_eff short by ~7e-9 per step of the run,
+// 2.6e-4 at 39 000 steps), while f' holds only the non-uniform part of the
+// flow, so the stall moves down by the ratio of the two.
+//
+// The drag enters through its deficit E = 1 - D = h / (kappa + h),
+// h = eps nu / 2, as tE = 2 tau E; with j' = sum e f', rho = rho0 + sum f':
+//   rho u_eq - U = 2 tau D (U + j' + rho eps G / 2) + (1 - 2 tau)(U + j') - U
+//               = j' + 2 tau rho eps G / 2 - tE (U + j' + rho eps G / 2),
+// every term of which is as small as the non-uniform flow or the drag.
+// tgx, tgy: 2 tau eps G / 2 of the item's drive; Ux, Uy: the reference U.
 template <typename P>
-__device__ __forceinline__ void collide(P f[9], P D, P hegx, P hegy, const Consts<P> &k)
+__device__ __forceinline__ void collide(P f[9], P tE, P hegx, P hegy, P tgx, P tgy, P Ux, P Uy,
+                                        const Consts<P> &k)
 {
     const P dr = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const P jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
     const P jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
     const P rho = P(1) + dr;
-    const P tD = k.twotau * D;
-    const P mx = tD * (jx + hegx * rho) + k.omtt * jx;
-    const P my = tD * (jy + hegy * rho) + k.omtt * jy;
+    const P mx = (jx + tgx * rho) - tE * (jx + (hegx * rho + Ux));
+    const P my = (jy + tgy * rho) - tE * (jy + (hegy * rho + Uy));
     const P om = k.om, omc = k.omc;
     const P s0 = (P(4) / P(9)) * om * dr;
     const P b = (P(1) / P(9)) * om * dr;
@@ -148,7 +190,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
     P *lds = reinterpret_cast<P *>(lds_raw);
     const Consts<P> kc(a);
     constexpr int NW = T / 64;
-    __shared__ double red[NW][2];
+    __shared__ double red[NW][4];
     __shared__ int ctrl[NW];  // item index per slot (at most NW slots), -1 = none
 
     const int tid = threadIdx.x;
@@ -158,12 +200,14 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
     int item = -1;
     int steps = 0;
     bool have_prev = false;
+    bool over_budget = false;  // FP32 item past esc_steps that cannot be re-run in FP64
     double prev_x = 0.0, prev_y = 0.0;
     int out = 0, x0 = 0, y0 = 0;
-    P hegx = 0, hegy = 0;
+    P hegx = 0, hegy = 0, tgx = 0, tgy = 0;
+    P Ux = 0, Uy = 0;  // reference momentum of the rebased state
     double hegx_d = 0.0, hegy_d = 0.0;
     // per-cell registers
-    P f0[CPT], Dc[CPT];
+    P f0[CPT], tE[CPT];  // rest population and 2 tau (1 - D) of each owned cell
     int xy[CPT];
 
     bool need_item = true;
@@ -196,8 +240,12 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                 hegy = drive == 1 ? kc.heg : P(0);
                 hegx_d = drive == 0 ? a.heg_d : 0.0;
                 hegy_d = drive == 1 ? a.heg_d : 0.0;
+                tgx = (P)(a.twotau_d * hegx_d);
+                tgy = (P)(a.twotau_d * hegy_d);
+                Ux = Uy = P(0);
                 steps = 0;
                 have_prev = false;
+                over_budget = false;
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     const int c = lt + k * G;
@@ -207,7 +255,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                         const int fx = (x0 + x) % a.fnx, fy = (y0 + y) % a.fny;
                         const double kap = a.field[(size_t)fy * a.fnx + fx];
                         // kappa <= 0 or NaN poisons the item: it ends flagged non-finite
-                        Dc[k] = (kap > 0.0) ? (P)(1.0 / (1.0 + a.h / kap))
+                        tE[k] = (kap > 0.0) ? (P)(a.twotau_d * a.h / (kap + a.h))
                                             : (P)__longlong_as_double(0x7ff8000000000000LL);
                         f0[k] = P(0);
 #pragma unroll
@@ -244,7 +292,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                             // own slots, in order; written back reversed
 #pragma unroll
                             for (int q = 1; q < 9; ++q) f[q] = A[(q - 1) * S2 + c];
-                            collide<P>(f, Dc[k], hegx, hegy, kc);
+                            collide<P>(f, tE[k], hegx, hegy, tgx, tgy, Ux, Uy, kc);
                             A[(3 - 1) * S2 + c] = f[1];
                             A[(4 - 1) * S2 + c] = f[2];
                             A[(1 - 1) * S2 + c] = f[3];
@@ -266,7 +314,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                             f[6] = A[(8 - 1) * S2 + rm + xp];
                             f[7] = A[(5 - 1) * S2 + rp + xp];
                             f[8] = A[(6 - 1) * S2 + rp + xm];
-                            collide<P>(f, Dc[k], hegx, hegy, kc);
+                            collide<P>(f, tE[k], hegx, hegy, tgx, tgy, Ux, Uy, kc);
                             // f*_a goes to A[a][x + e_a]
                             A[(1 - 1) * S2 + r0 + xp] = f[1];
                             A[(2 - 1) * S2 + rp + x] = f[2];
@@ -287,7 +335,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
         if (active) steps += a.check_every;
 
         // ---- convergence check: FP64 mean velocity of each slot --------------
-        double sx = 0.0, sy = 0.0;
+        double sx = 0.0, sy = 0.0, qx = 0.0, qy = 0.0;  // sums of u (inner window) and of j'
         if (active) {
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
@@ -299,10 +347,13 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
 #pragma unroll
                     for (int q = 1; q < 9; ++q) fd[q] = (double)A[(q - 1) * S2 + c];
                     const double dr = ((fd[0] + fd[1]) + (fd[2] + fd[3])) + ((fd[4] + fd[5]) + (fd[6] + fd[7])) + fd[8];
-                    const double jx = (fd[1] - fd[3]) + ((fd[5] - fd[6]) + (fd[8] - fd[7]));
-                    const double jy = (fd[2] - fd[4]) + ((fd[5] + fd[6]) - (fd[7] + fd[8]));
+                    const double jpx = (fd[1] - fd[3]) + ((fd[5] - fd[6]) + (fd[8] - fd[7]));
+                    const double jpy = (fd[2] - fd[4]) + ((fd[5] + fd[6]) - (fd[7] + fd[8]));
+                    qx += jpx;
+                    qy += jpy;
+                    const double jx = (double)Ux + jpx, jy = (double)Uy + jpy;
                     const double rho = 1.0 + dr;
-                    const double D = (double)Dc[k];
+                    const double D = 1.0 - (double)tE[k] / a.twotau_d;
                     // oversampling: only the inner window enters the average
                     const int x = xy[k] & 255, y = xy[k] >> 8;
                     const int m = a.margin;
@@ -315,17 +366,23 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
         }
         sx = wave_sum(sx);
         sy = wave_sum(sy);
+        qx = wave_sum(qx);
+        qy = wave_sum(qy);
         if ((tid & 63) == 0) {
             red[tid >> 6][0] = sx;
             red[tid >> 6][1] = sy;
+            red[tid >> 6][2] = qx;
+            red[tid >> 6][3] = qy;
         }
         __syncthreads();
         if (active) {
             const int w0 = (slot * G) >> 6, nw = G >> 6;
-            double tx = 0.0, ty = 0.0;
+            double tx = 0.0, ty = 0.0, tqx = 0.0, tqy = 0.0;
             for (int w = 0; w < nw; ++w) {
                 tx += red[w0 + w][0];
                 ty += red[w0 + w][1];
+                tqx += red[w0 + w][2];
+                tqy += red[w0 + w][3];
             }
             const double inner = (double)(S - 2 * a.margin) * (double)(S - 2 * a.margin);
             const double ux = tx / inner, uy = ty / inner;
@@ -337,10 +394,28 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                 if (sqrt(dx * dx + dy * dy) <= a.tol * sqrt(ux * ux + uy * uy)) flag = 0;
             }
             if (flag == -2 && steps >= a.max_steps) flag = 1;
+            // Past the FP32 step budget: a slowly converging item whose FP32
+            // state would stop short of the fixed point by more than the
+            // target (the stall grows with the relaxation time). Hand it to
+            // the FP64 re-run, or, where FP64 state does not fit, finish in
+            // FP32 and say so in the flag.
+            if (flag == -2 && a.esc_steps > 0 && steps >= a.esc_steps) {
+                if (cd.esc_ok)
+                    flag = 4;
+                else
+                    over_budget = true;
+            }
+            if (flag == 0 && over_budget) flag = 3;
             prev_x = ux;
             prev_y = uy;
             have_prev = true;
-            if (flag != -2) {
+            if (flag == 4) {
+                if (lt == 0) {
+                    const int pos = atomicAdd(&a.esc_classes[cls].count, 1);
+                    a.esc_items[a.esc_classes[cls].begin + pos] = make_int4(x0, y0, S, out);
+                }
+                need_item = true;
+            } else if (flag != -2) {
                 if (lt == 0) {
                     const int patch = out >> 1, drive = out & 1;
                     a.keff[4 * (size_t)patch + drive] = a.nu_over_g * ux;
@@ -349,6 +424,32 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                     if (a.flags_out) a.flags_out[2 * patch + drive] = flag;
                 }
                 need_item = true;
+            } else {
+                // rebase on the item's current mean momentum U + mean j':
+                // f' -= 3 w_a e_a . (U_new - U); U_new is kept in the storage
+                // type, so the stored state and U describe the same f
+                const P nUx = reference_momentum<P>((double)Ux + tqx / (double)S2);
+                const P nUy = reference_momentum<P>((double)Uy + tqy / (double)S2);
+                const P dUx = nUx - Ux, dUy = nUy - Uy;
+                Ux = nUx;
+                Uy = nUy;
+                const P ax = P(1) / P(3) * dUx, ay = P(1) / P(3) * dUy;              // 3 w_a e_a . dU, axes
+                const P dp = P(1) / P(12) * (dUx + dUy), dm = P(1) / P(12) * (dUx - dUy);  // diagonals
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    const int c = lt + k * G;
+                    if (k < C && c < S2) {
+                        // even order: A[a - 1][c] holds f'_a of cell c
+                        A[0 * S2 + c] -= ax;
+                        A[1 * S2 + c] -= ay;
+                        A[2 * S2 + c] += ax;
+                        A[3 * S2 + c] += ay;
+                        A[4 * S2 + c] -= dp;
+                        A[5 * S2 + c] += dm;
+                        A[6 * S2 + c] += dp;
+                        A[7 * S2 + c] -= dm;
+                    }
+                }
             }
         }
         __syncthreads();  // red[] and ctrl[] are reused
@@ -464,7 +565,8 @@ __global__ void k_local_scatter(int n, const int4 *__restrict__ items, const int
 }
 
 struct LocalLayout {
-    size_t off_items, off_classes, off_counters, off_mask, off_sorted, off_keys, total;
+    size_t off_items, off_classes, off_counters, off_mask, off_sorted, off_keys, off_esc_items, off_esc_classes,
+        off_esc_counters, total;
 };
 
 // counters: kMaxClasses item counters, then the schedule histogram and its
@@ -483,6 +585,9 @@ LocalLayout local_layout(int n_patches)
     L.off_mask = off;     off = align_up(off + sizeof(int) * (size_t)std::max(n_patches, 1));
     L.off_sorted = off;   off = align_up(off + sizeof(int4) * items);
     L.off_keys = off;     off = align_up(off + sizeof(int) * items);
+    L.off_esc_items = off;    off = align_up(off + sizeof(int4) * items);
+    L.off_esc_classes = off;  off = align_up(off + sizeof(ClassDesc) * kMaxClasses);
+    L.off_esc_counters = off; off = align_up(off + sizeof(int) * kMaxClasses);
     L.total = off;
     return L;
 }
@@ -577,6 +682,7 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     if (lp->avg_margin < 0) return set_error(LBM_EINVAL, std::string(fn) + "avg_margin must be >= 0");
     if (lp->schedule != LBM_SCHEDULE_GIVEN && lp->schedule != LBM_SCHEDULE_COST)
         return set_error(LBM_EINVAL, std::string(fn) + "unknown schedule");
+    if (lp->fp32_step_budget < 0) return set_error(LBM_EINVAL, std::string(fn) + "fp32_step_budget must be >= 0");
     if (n_patches < 0) return set_error(LBM_EINVAL, std::string(fn) + "n_patches < 0");
     if (n_patches == 0) return LBM_OK;
     if (!h_x0 || !h_y0 || !h_side || !h_drive_mask || !d_kappa_field || !d_keff)
@@ -714,6 +820,13 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     a.margin = lp->avg_margin;
     const int64_t ms = (lp->max_steps + lp->check_every - 1) / lp->check_every * lp->check_every;
     a.max_steps = (int)std::min<int64_t>(ms, (int64_t)1 << 30);
+    // FP32 step budget (FP32 state only): rounded up to a check; a budget at
+    // or beyond the step cap never triggers
+    const bool escalate = !f64 && lp->fp32_step_budget > 0 &&
+                          (int64_t)lp->fp32_step_budget < (int64_t)a.max_steps;
+    a.esc_steps = escalate ? (int)((lp->fp32_step_budget + lp->check_every - 1) / lp->check_every *
+                                   lp->check_every)
+                           : 0;
     // One persistent launch per register shape: each is compiled for the most
     // cells any of its threads owns (1, 2 or 4), since a launch for single
     // cells keeps fewer registers live and fits two workgroups per CU. When a
@@ -731,14 +844,50 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     const int n_multi = (int)grouped.size();
     for (const ClassDesc &c : classes)
         if (c.cells_per_thread <= 1) grouped.push_back(c);
+    // The FP64 re-run of items past the FP32 step budget: one class per
+    // grouped class (same item ranges, in a queue of its own), laid out for
+    // FP64 state on kEscThreads threads with as many threads per item as the
+    // side allows (the re-run items are few and long, so per-item latency
+    // matters more than items per CU); sides whose FP64 state does not fit
+    // stay in FP32.
+    std::vector<ClassDesc> esc(grouped.size());
+    size_t esc_lds = 0;
+    int esc_cpt = 1;
+    for (size_t i = 0; i < grouped.size(); ++i) {
+        ClassDesc c = grouped[i];
+        const int cells = c.side * c.side;
+        const int G = std::min(kEscThreads, std::max(64, pow2_at_least(cells)));
+        c.slot_threads = G;
+        c.cells_per_thread = (cells + G - 1) / G;
+        c.nslots = kEscThreads / G;
+        c.count = 0;  // filled by the FP32 launch
+        c.esc_ok = escalate && c.cells_per_thread <= kCPT && (size_t)64 * cells <= (size_t)budget;
+        while (c.nslots > 1 && (size_t)c.nslots * 64 * cells > (size_t)budget) --c.nslots;
+        if (c.esc_ok) {
+            esc_lds = std::max(esc_lds, (size_t)c.nslots * 64 * cells);
+            esc_cpt = std::max(esc_cpt, c.cells_per_thread);
+        }
+        grouped[i].esc_ok = c.esc_ok;
+        esc[i] = c;
+    }
+    const bool any_esc = std::any_of(esc.begin(), esc.end(), [](const ClassDesc &c) { return c.esc_ok != 0; });
     ClassDesc *d_grouped = d_classes + kMaxClasses;
     LBM_HIP(hipMemcpyAsync(d_grouped, grouped.data(), sizeof(ClassDesc) * grouped.size(), hipMemcpyHostToDevice,
                            stream));
+    ClassDesc *d_esc = reinterpret_cast<ClassDesc *>(ws + L.off_esc_classes);
+    int *d_esc_counters = reinterpret_cast<int *>(ws + L.off_esc_counters);
+    int4 *d_esc_items = reinterpret_cast<int4 *>(ws + L.off_esc_items);
+    if (any_esc) {
+        LBM_HIP(hipMemcpyAsync(d_esc, esc.data(), sizeof(ClassDesc) * esc.size(), hipMemcpyHostToDevice, stream));
+        LBM_HIP(hipMemsetAsync(d_esc_counters, 0, sizeof(int) * esc.size(), stream));
+    }
     auto launch_group = [&](int first, int count, hipStream_t st) -> lbm_status {
         LocalArgs g = a;
         g.classes = d_grouped + first;
         g.nclasses = count;
         g.counters = d_counters + first;
+        g.esc_classes = d_esc + first;
+        g.esc_items = d_esc_items;
         int cmax = 1, need = 0;
         size_t lds = 0;
         for (int i = first; i < first + count; ++i) {
@@ -756,9 +905,32 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
         if (T == 512) return launch_local<512, float>(g, lds, grid, cpt, st);
         return launch_local<1024, float>(g, lds, grid, cpt, st);
     };
+    // The FP64 re-run, queued on `stream` after the FP32 launch(es): a
+    // persistent launch over the re-run queues, whose workgroups leave at
+    // once when the queues are empty.
+    auto launch_esc = [&]() -> lbm_status {
+        if (!any_esc) return LBM_OK;
+        LocalArgs e = a;
+        e.items = d_esc_items;
+        e.classes = d_esc;
+        e.nclasses = (int)esc.size();
+        e.counters = d_esc_counters;
+        e.esc_steps = 0;
+        e.esc_classes = nullptr;
+        e.esc_items = nullptr;
+        int potential = 0;  // workgroups the queues could use at most
+        for (size_t i = 0; i < esc.size(); ++i)
+            if (esc[i].esc_ok) potential = std::max(potential, (grouped[i].count + esc[i].nslots - 1) / esc[i].nslots);
+        const int cpt = esc_cpt <= 1 ? 1 : (esc_cpt <= 2 ? 2 : 4);
+        return launch_local<kEscThreads, double>(e, esc_lds, std::max(1, potential), cpt, stream);
+    };
     const int n_single = (int)grouped.size() - n_multi;
     hipStream_t side = (n_multi > 0 && n_single > 0) ? side_stream() : nullptr;
-    if (!side) return launch_group(0, (int)grouped.size(), stream);
+    if (!side) {
+        const lbm_status st = launch_group(0, (int)grouped.size(), stream);
+        if (st != LBM_OK) return st;
+        return launch_esc();
+    }
     hipEvent_t fork = nullptr, join = nullptr;
     LBM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
@@ -780,5 +952,5 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     (void)hipEventDestroy(join);
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return hip_check(e, "lbm_local_keff: stream fork/join");
-    return LBM_OK;
+    return launch_esc();
 }

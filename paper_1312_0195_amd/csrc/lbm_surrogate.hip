@@ -189,12 +189,16 @@ __device__ __forceinline__ void block_sum3_fixed(float &a, float &b, float &c, f
 
 // conv1 (1 -> 32 channels) on MFMA: the nine taps are the K dimension (padded
 // to 32 with zeros), BF16 inputs and weights, FP32 accumulation, bias and
-// ReLU in FP32; output [pixel][channel] BF16 as the other layers.
+// ReLU in FP32; output [pixel][channel] BF16 as the other layers. As in the
+// 32 -> 32 layers the weights are the A operand (16 output channels x 32
+// taps) and the taps of 16 pixels the B operand, so each lane ends with four
+// consecutive channels of one pixel and stores them with one 8-byte write.
 __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 *__restrict__ out,
                                            const float *__restrict__ prm, __bf16 *__restrict__ gout)
 {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = lane & 15, g = lane >> 4;
+    const int n = lane & 15, g = lane >> 4;  // n: output channel row of A / pixel of B; g: k-group
     bf16x8 w0, w1;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -202,7 +206,12 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
         w0[j] = (__bf16)(t < 9 ? prm[oW1 + t * kC + n] : 0.0f);
         w1[j] = (__bf16)(t < 9 ? prm[oW1 + t * kC + 16 + n] : 0.0f);
     }
-    const float b0 = prm[oB1 + n], b1 = prm[oB1 + 16 + n];
+    float b0[4], b1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        b0[i] = prm[oB1 + g * 4 + i];
+        b1[i] = prm[oB1 + 16 + g * 4 + i];
+    }
     for (int tile = wave; tile < kPix / 16; tile += kWaves) {
         const int y = tile >> 1, x0 = (tile & 1) * 16;
         bf16x8 a;
@@ -214,18 +223,20 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
             a[j] = (__bf16)(t < 9 ? v : 0.0f);
         }
         const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-        const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w0, z, 0, 0, 0);
-        const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1, z, 0, 0, 0);
+        const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, a, z, 0, 0, 0);
+        const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, a, z, 0, 0, 0);
+        const int p = y * kSide + x0 + n;  // D column = pixel
+        bf16x4 v0, v1;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int p = y * kSide + x0 + g * 4 + i;
-            const __bf16 v0 = (__bf16)fmaxf(acc0[i] + b0, 0.0f), v1 = (__bf16)fmaxf(acc1[i] + b1, 0.0f);
-            out[p * kC + n] = v0;
-            out[p * kC + 16 + n] = v1;
-            if (gout) {
-                gout[p * kC + n] = v0;
-                gout[p * kC + 16 + n] = v1;
-            }
+            v0[i] = (__bf16)fmaxf(acc0[i] + b0[i], 0.0f);
+            v1[i] = (__bf16)fmaxf(acc1[i] + b1[i], 0.0f);
+        }
+        *reinterpret_cast<bf16x4 *>(out + p * kC + g * 4) = v0;
+        *reinterpret_cast<bf16x4 *>(out + p * kC + 16 + g * 4) = v1;
+        if (gout) {
+            *reinterpret_cast<bf16x4 *>(gout + p * kC + g * 4) = v0;
+            *reinterpret_cast<bf16x4 *>(gout + p * kC + 16 + g * 4) = v1;
         }
     }
 }
@@ -255,6 +266,7 @@ struct FwdArgs {
     int batch;
     float *pred;            // [B][2] log kxx, log kyy
     float *stats;           // [B][8] mean, std, lag-1 corr x, y, the 4 features (or null)
+    float *spread;          // [B][2] max - min over the n_sym predictions (or null)
     __bf16 *acts;           // [4][B][1024][32] when training, else null
     float *pool_out;        // [B][37] head input when training
     int *next;              // patches claimed beyond the first gridDim.x (zeroed by k_pack)
@@ -368,6 +380,7 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     for (int b = blockIdx.x; b < a.batch;) {
         const float *lk = a.logk + (size_t)b * kPix;
         float acc0 = 0.0f, acc1 = 0.0f;  // averaged prediction (thread 0)
+        float lo0 = INFINITY, hi0 = -INFINITY, lo1 = INFINITY, hi1 = -INFINITY;  // their range
         for (int t = 0; t < a.n_sym; ++t) {
             const int sym = a.sym ? (int)a.sym[b] : t;
             // ---- input under the symmetry, centring (FP32) ----
@@ -449,8 +462,13 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
                     s0 += prm[oC2] + m;
                     s1 += prm[oC2 + 1] + m;
                     // a transposed patch predicts (kyy, kxx) of the original
-                    acc0 += (sym & 1) ? s1 : s0;
-                    acc1 += (sym & 1) ? s0 : s1;
+                    const float q0 = (sym & 1) ? s1 : s0, q1 = (sym & 1) ? s0 : s1;
+                    acc0 += q0;
+                    acc1 += q1;
+                    lo0 = fminf(lo0, q0);
+                    hi0 = fmaxf(hi0, q0);
+                    lo1 = fminf(lo1, q1);
+                    hi1 = fmaxf(hi1, q1);
                 }
             }
             __syncthreads();
@@ -458,6 +476,10 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
         if (tid == 0) {
             a.pred[2 * (size_t)b] = acc0 / a.n_sym;
             a.pred[2 * (size_t)b + 1] = acc1 / a.n_sym;
+            if (a.spread) {
+                a.spread[2 * (size_t)b] = hi0 - lo0;
+                a.spread[2 * (size_t)b + 1] = hi1 - lo1;
+            }
             claimed = (int)gridDim.x + atomicAdd(a.next, 1);
         }
         // every thread reads the claim before the next write to it, which
@@ -831,9 +853,10 @@ lbm_status pack(const float *prm, char *ws, const SurLayout &L, hipStream_t stre
 
 lbm_status forward(const float *prm, int batch, const float *logk, const int8_t *sym, int n_sym, float *pred,
                    float *stats, char *ws, const SurLayout &L, bool train, hipStream_t stream,
-                   int max_workgroups = 0)
+                   int max_workgroups = 0, float *spread = nullptr)
 {
     FwdArgs a{};
+    a.spread = spread;
     a.prm = prm;
     a.wf = reinterpret_cast<const __bf16 *>(ws + L.off_wf);
     a.logk = logk;
@@ -973,6 +996,24 @@ extern "C" lbm_status lbm_cnn_forward_noalloc(const float *d_params, int32_t bat
     if (s != LBM_OK) return s;
     return forward(d_params, batch, d_logk, nullptr, n_sym, d_pred, d_stats, ws, L, false, stream,
                    max_workgroups);
+}
+
+extern "C" lbm_status lbm_cnn_forward_spread(const float *d_params, int32_t batch, const float *d_logk,
+                                             int32_t n_sym, float *d_pred, float *d_spread, int32_t max_workgroups,
+                                             void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (batch < 1 || !d_params || !d_logk || !d_pred || !d_spread)
+        return set_error(LBM_EINVAL, "lbm_cnn_forward_spread: batch < 1 or NULL argument");
+    if (n_sym < 1 || n_sym > 8) return set_error(LBM_EINVAL, "lbm_cnn_forward_spread: n_sym must lie in [1, 8]");
+    if (max_workgroups < 0) return set_error(LBM_EINVAL, "lbm_cnn_forward_spread: max_workgroups must be >= 0");
+    const SurLayout L = sur_layout(batch, false);
+    lbm_status s = check_ws(d_ws, ws_bytes, L.total, "lbm_cnn_forward_spread");
+    if (s != LBM_OK) return s;
+    char *ws = static_cast<char *>(d_ws);
+    s = pack(d_params, ws, L, stream);
+    if (s != LBM_OK) return s;
+    return forward(d_params, batch, d_logk, nullptr, n_sym, d_pred, nullptr, ws, L, false, stream, max_workgroups,
+                   d_spread);
 }
 
 extern "C" lbm_status lbm_cnn_forward(const float *d_params, int32_t batch, const float *d_logk, int32_t n_sym,

@@ -18,11 +18,19 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EDEVICE, LBM_ENOTCONV, LBM_ENONFINITE, LBM_EWORKSPACE = 0, -1, -2, -3, -4, -5
-LBM_F32_SHIFTED, LBM_F64 = 0, 1
+LBM_F32_SHIFTED, LBM_F64, LBM_F32_FAST = 0, 1, 2
 LBM_PERM_SCALAR, LBM_PERM_TENSOR = 1, 4
 LBM_SCHEME_SHAN_CHEN, LBM_SCHEME_GUO = 0, 1
 LBM_SCHEDULE_GIVEN, LBM_SCHEDULE_COST = 0, 1
 LBM_KEFF_SCALAR, LBM_KEFF_TENSOR = 0, 1
+
+#: default FP32 step budget of the local problems (0: none). The FP32 state
+#: is stored rebased on each item's mean momentum, which keeps every tensor
+#: within 1e-4 of the fixed point relative to its largest diagonal entry; a
+#: nearly blocked direction of a very heterogeneous patch (kappa spanning ten
+#: e-folds) can still be short by a few 1e-4 of its own small value, and a
+#: budget such as 10 000 steps re-runs those slow items with FP64 state.
+FP32_STEP_BUDGET = 0
 
 #: every symbol the header declares (checked against include/lbm.h by the tests)
 EXPORTS = (
@@ -32,7 +40,7 @@ EXPORTS = (
     "lbm_coarse_workspace_bytes", "lbm_coarse_solve", "lbm_block_average", "lbm_status_str",
     "lbm_last_error",
     "lbm_cnn_param_count", "lbm_cnn_workspace_bytes", "lbm_cnn_forward", "lbm_cnn_forward_limited",
-    "lbm_cnn_forward_noalloc",
+    "lbm_cnn_forward_noalloc", "lbm_cnn_forward_spread",
     "lbm_cnn_gradients",
     "lbm_cnn_train_step", "lbm_patch_stats",
     "lbm3d_workspace_bytes", "lbm3d_init", "lbm3d_step", "lbm3d_fields", "lbm3d_get_populations",
@@ -66,7 +74,7 @@ class lbm_local_params(ctypes.Structure):
                 ("g", ctypes.c_double), ("tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("max_steps", ctypes.c_int64),
                 ("pop_dtype", ctypes.c_int32), ("avg_margin", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("fp32_step_budget", ctypes.c_int32)]
 
 
 class lbm_local_tile(ctypes.Structure):
@@ -162,6 +170,9 @@ def lib():
     L.lbm_cnn_forward_noalloc.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
                                           _vp]
     L.lbm_cnn_forward_noalloc.restype = ctypes.c_int
+    L.lbm_cnn_forward_spread.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
+                                         _vp, ctypes.c_size_t, _vp]
+    L.lbm_cnn_forward_spread.restype = ctypes.c_int
     L.lbm_cnn_gradients.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp]
     L.lbm_cnn_gradients.restype = ctypes.c_int
@@ -381,6 +392,13 @@ def lbm_cnn_forward_limited(d_params, batch, d_logk, n_sym, d_pred, d_stats, max
                                          int(ws_bytes), _stream(stream)), "lbm_cnn_forward_limited")
 
 
+def lbm_cnn_forward_spread(d_params, batch, d_logk, n_sym, d_pred, d_spread, max_workgroups, d_ws,
+                           ws_bytes, stream=None) -> None:
+    _raise(lib().lbm_cnn_forward_spread(_ptr(d_params), int(batch), _ptr(d_logk), int(n_sym),
+                                        _ptr(d_pred), _ptr(d_spread), int(max_workgroups), _ptr(d_ws),
+                                        int(ws_bytes), _stream(stream)), "lbm_cnn_forward_spread")
+
+
 def lbm_cnn_forward_noalloc(d_params, batch, d_logk, n_sym, d_pred, d_stats, max_workgroups=0,
                             stream=None) -> None:
     _raise(lib().lbm_cnn_forward_noalloc(_ptr(d_params), int(batch), _ptr(d_logk), int(n_sym),
@@ -556,11 +574,13 @@ class LocalResult:
 def local_keff(kappa_field, x0, y0, side, tau, eps, nu, g=1e-6, tol=1e-6, check_every=100,
                max_steps=200000, drive_mask=None, tiles=None, block_threads=0, device="cuda",
                kappa_dev=None, use_tuned=True, pop_dtype=LBM_F32_SHIFTED,
-               avg_margin=0, schedule=None) -> LocalResult:
+               avg_margin=0, schedule=None, fp32_step_budget=None) -> LocalResult:
     """Run lbm_local_keff on a field (host array or device tensor) and return
     host results. Without explicit tiles, the autotuned table is used when
     one exists (see paper_1312_0195_amd.autotune); without an explicit
-    schedule, the table's, else LBM_SCHEDULE_COST."""
+    schedule, the table's, else LBM_SCHEDULE_COST. fp32_step_budget: FP32
+    items still running after this many steps are re-run with FP64 state
+    (default FP32_STEP_BUDGET; 0 = never)."""
     import torch
     if tiles is None and block_threads == 0 and use_tuned:
         from .autotune import load_table
@@ -578,9 +598,10 @@ def local_keff(kappa_field, x0, y0, side, tau, eps, nu, g=1e-6, tol=1e-6, check_
     flags = torch.empty((n, 2), dtype=torch.int32, device=dev)
     nbytes = lbm_local_workspace_bytes(n)
     ws = _workspace(nbytes, dev)
+    budget = FP32_STEP_BUDGET if fp32_step_budget is None else fp32_step_budget
     lp = lbm_local_params(float(tau), float(eps), float(nu), float(g), float(tol),
                           int(check_every), int(max_steps), int(pop_dtype), int(avg_margin),
-                          int(schedule))
+                          int(schedule), int(budget))
     dm = np.full(n, 3, np.int32) if drive_mask is None else drive_mask
     lbm_local_keff(lp, x0, y0, side, dm, kd, keff, steps, flags, tiles, block_threads, ws,
                    nbytes)

@@ -11,9 +11,13 @@ problems of Sec. 3 give through Eq. tensor-kappa. This module:
   Adam kernels (lbm_cnn_train_step);
 * trains with a random symmetry of the square per patch (the kernel applies
   it as it reads the patch) and predicts with the mean over all eight;
-* predicts with lbm_cnn_forward, flags patches whose statistics (standard
-  deviation and lag-1 correlations of log K, computed by the same kernel) fall
-  outside the ranges seen in training, and sends those to lbm_local_keff.
+* predicts with the library's forward kernels and sends to lbm_local_keff
+  the patches it should not trust, in two stages: before the network runs,
+  those whose statistics (computed by lbm_patch_stats) lie far from the
+  training distribution (Mahalanobis distance of the detector features);
+  after it, those whose symmetric predictions disagree (the spread that
+  lbm_cnn_forward_spread returns). Both thresholds are quantiles over
+  unlabelled in-range patches, so they need no LBM labels.
 
 Device memory comes from torch; all arithmetic runs in the HIP library.
 """
@@ -119,10 +123,11 @@ def training_set(n_patches: int, seed: int = 1, field_side: int = 256,
 def detector_features(stats) -> np.ndarray:
     """Features of the range detector from the kernel's per-patch statistics
     (mean, std, lag-1 correlation along x, along y, then the series/parallel
-    estimates sx_lo, sx_up, sy_lo, sy_up): std, both correlations, their
-    difference (anisotropy, e.g. channels), and when present the gap between
-    the upper and lower estimate in each direction (contrast and its
-    connectivity) and the difference of the two upper estimates."""
+    estimates sx_lo, sx_up, sy_lo, sy_up): std, both correlations, the gap
+    between the upper and lower estimate in each direction (contrast and its
+    connectivity) and the difference of the two upper estimates (anisotropy,
+    e.g. channels). No column is a linear combination of others, so their
+    covariance over in-range patches is invertible."""
     return np.stack(list(_feature_columns(np.asarray(stats, dtype=np.float64))), axis=1)
 
 
@@ -130,20 +135,23 @@ def _feature_columns(s):
     yield s[:, 1]
     yield s[:, 2]
     yield s[:, 3]
-    yield s[:, 2] - s[:, 3]
-    if s.shape[1] >= 8:
-        yield s[:, 5] - s[:, 4]
-        yield s[:, 7] - s[:, 6]
-        yield s[:, 5] - s[:, 7]
+    yield s[:, 5] - s[:, 4]
+    yield s[:, 7] - s[:, 6]
+    yield s[:, 5] - s[:, 7]
 
 
 @dataclass
 class Surrogate:
     params: np.ndarray
-    stat_lo: np.ndarray = field(default_factory=lambda: np.full(7, -np.inf))
-    stat_hi: np.ndarray = field(default_factory=lambda: np.full(7, np.inf))
+    # range detector: mean and inverse covariance of detector_features over
+    # in-range patches, the largest accepted squared Mahalanobis distance, and
+    # the largest accepted spread of the symmetric predictions (log units)
+    det_mean: np.ndarray = field(default_factory=lambda: np.zeros(6))
+    det_icov: np.ndarray = field(default_factory=lambda: np.zeros((6, 6)))
+    det_d2_max: float = np.inf
+    spread_max: float = np.inf
     history: list = field(default_factory=list)
-    n_sym: int = 8
+    n_sym: int = 2
 
     @classmethod
     def new(cls, seed: int = 0) -> "Surrogate":
@@ -151,7 +159,7 @@ class Surrogate:
 
     # -- training ----------------------------------------------------------
     def fit(self, logk, target, epochs=20, batch=256, lr=2e-3, lr_final=1e-4, seed=0,
-            device="cuda", augment=True, verbose=False):
+            device="cuda", augment=True, verbose=False, calibrate=True):
         import torch
         dev = torch.device(device)
         n = len(logk)
@@ -191,17 +199,43 @@ class Surrogate:
                 print(f"epoch {ep + 1}/{epochs}: loss {mean_loss:.3e} "
                       f"({time.perf_counter() - t0:.1f} s)", flush=True)
         self.params = prm.cpu().numpy()
-        self.calibrate(logk, device=device)
+        if calibrate:
+            self.calibrate(logk, device=device)
         return self
 
-    def calibrate(self, logk, q=0.001, pad=0.05, device="cuda"):
-        """Range detector: per feature, the [q, 1 - q] quantiles over the
-        training patches, widened by pad times their spread."""
+    def calibrate(self, logk, q_feat=0.99, q_spread=0.95, device="cuda"):
+        """Range detector from unlabelled in-range patches: the mean and
+        covariance of the detector features, the q_feat quantile of their
+        squared Mahalanobis distance, and the q_spread quantile of the spread
+        of the model's n_sym symmetric predictions (the larger of the two
+        outputs' spreads)."""
         _, stats = self.predict(logk, device=device, n_sym=1)
-        s = detector_features(stats)
-        lo, hi = np.quantile(s, q, axis=0), np.quantile(s, 1.0 - q, axis=0)
-        self.stat_lo, self.stat_hi = lo - pad * (hi - lo), hi + pad * (hi - lo)
+        f = detector_features(stats)
+        self.det_mean = f.mean(axis=0)
+        self.det_icov = np.linalg.inv(np.cov(f.T))
+        self.det_d2_max = float(np.quantile(self.distance2(stats), q_feat))
+        _, spread = self.predict_spread(logk, device=device)
+        self.spread_max = float(np.quantile(spread.max(axis=1), q_spread))
         return self
+
+    # -- the range detector --------------------------------------------------
+    def distance2(self, stats) -> np.ndarray:
+        """Squared Mahalanobis distance of each patch's detector features from
+        the in-range patches' mean (NaN features give +inf)."""
+        d = detector_features(stats) - self.det_mean
+        d2 = np.einsum("ij,jk,ik->i", d, self.det_icov, d)
+        return np.where(np.isfinite(d2), d2, np.inf)
+
+    def in_range(self, stats) -> np.ndarray:
+        """Stage one (statistics only, before the network runs): patches
+        whose features lie within the calibrated distance."""
+        return self.distance2(stats) <= self.det_d2_max
+
+    def confident(self, spread) -> np.ndarray:
+        """Stage two (after the network): patches whose symmetric
+        predictions agree to within the calibrated spread (NaN: not)."""
+        s = np.asarray(spread, dtype=np.float64).max(axis=1)
+        return np.where(np.isfinite(s), s, np.inf) <= self.spread_max
 
     # -- inference ---------------------------------------------------------
     def predict(self, logk, device="cuda", batch=65536, n_sym=None):
@@ -227,31 +261,47 @@ class Surrogate:
             stats.append(st.cpu().numpy())
         return np.concatenate(preds).astype(np.float64), np.concatenate(stats).astype(np.float64)
 
-    def in_range(self, stats) -> np.ndarray:
-        # column by column (no feature matrix): the same comparisons as
-        # against detector_features(stats), without its copies
-        s = np.asarray(stats, dtype=np.float64)
-        ok = np.ones(len(s), bool)
-        for j, col in zip(range(len(self.stat_lo)), _feature_columns(s)):
-            ok &= col >= self.stat_lo[j]
-            ok &= col <= self.stat_hi[j]
-        return ok
+    def predict_spread(self, logk, device="cuda", batch=65536, n_sym=None):
+        """(pred [n, 2], spread [n, 2]): the mean and the range of the n_sym
+        symmetric predictions (lbm_cnn_forward_spread)."""
+        n_sym = self.n_sym if n_sym is None else n_sym
+        import torch
+        dev = torch.device(device)
+        logk = np.ascontiguousarray(logk, np.float32)
+        prm = torch.as_tensor(self.params).to(dev)
+        preds, spreads = [], []
+        for s in range(0, len(logk), batch):
+            xb = torch.as_tensor(logk[s:s + batch]).to(dev)
+            b = len(xb)
+            pred = torch.empty((b, 2), dtype=torch.float32, device=dev)
+            spr = torch.empty((b, 2), dtype=torch.float32, device=dev)
+            nb = L.lbm_cnn_workspace_bytes(b, False)
+            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            L.lbm_cnn_forward_spread(prm, b, xb, n_sym, pred, spr, 0, ws, nb)
+            preds.append(pred.cpu().numpy())
+            spreads.append(spr.cpu().numpy())
+        return np.concatenate(preds).astype(np.float64), np.concatenate(spreads).astype(np.float64)
 
     def save(self, path):
-        np.savez(path, params=self.params, stat_lo=self.stat_lo, stat_hi=self.stat_hi,
+        np.savez(path, params=self.params, det_mean=self.det_mean, det_icov=self.det_icov,
+                 det_d2_max=np.float64(self.det_d2_max), spread_max=np.float64(self.spread_max),
                  history=np.asarray(self.history), n_sym=np.int32(self.n_sym))
 
     @classmethod
     def load(cls, path) -> "Surrogate":
         d = np.load(path)
-        return cls(d["params"].astype(np.float32), d["stat_lo"], d["stat_hi"],
-                   list(d["history"]), int(d["n_sym"]) if "n_sym" in d else 8)
+        m = cls(d["params"].astype(np.float32), history=list(d["history"]),
+                n_sym=int(d["n_sym"]) if "n_sym" in d else 2)
+        if "det_mean" in d:
+            m.det_mean, m.det_icov = d["det_mean"], d["det_icov"]
+            m.det_d2_max, m.spread_max = float(d["det_d2_max"]), float(d["spread_max"])
+        return m
 
 
 def _local_keff_launch(kappa_dev, x0, y0, tol=1e-7):
     """Enqueue lbm_local_keff for 32 x 32 windows on the current stream
-    without waiting; returns the device K_eff tensor [n, 4] (and the buffers
-    that must outlive the launch)."""
+    without waiting; returns the device K_eff tensor [n, 4], the device flags
+    [n, 2] and the workspace (which must outlive the launch)."""
     import torch
     from .autotune import load_schedule, load_table
     n = len(x0)
@@ -259,36 +309,38 @@ def _local_keff_launch(kappa_dev, x0, y0, tol=1e-7):
     block, tiles = load_table()
     sched = load_schedule()
     keff = torch.empty((n, 4), dtype=torch.float64, device=dev)
+    flags = torch.empty((n, 2), dtype=torch.int32, device=dev)
     nb = L.lbm_local_workspace_bytes(n)
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
     lp = L.lbm_local_params(PHYS["tau"], PHYS["eps"], PHYS["nu"], PHYS["g"], float(tol), 100, 400000,
-                            L.LBM_F32_SHIFTED, 0, L.LBM_SCHEDULE_COST if sched is None else sched)
+                            L.LBM_F32_SHIFTED, 0, L.LBM_SCHEDULE_COST if sched is None else sched,
+                            L.FP32_STEP_BUDGET)
     L.lbm_local_keff(lp, x0, y0, np.full(n, SIDE, np.int32), np.full(n, 3, np.int32), kappa_dev, keff,
-                     None, None, tiles, block, ws, nb)
-    return keff, ws
+                     None, flags, tiles, block, ws, nb)
+    return keff, flags, ws
 
 
-def keff_with_fallback(model: Surrogate, kappa_dev, x0, y0, logk_dev, n_sym=None, lbm_first=False,
+def keff_with_fallback(model: Surrogate, kappa_dev, x0, y0, logk_dev, n_sym=None,
                        network_workgroups=None):
     """log kxx, log kyy of the 32 x 32 windows at (x0, y0) of the device field
-    kappa_dev, whose log patches are logk_dev (FP32 [n, 32, 32], device):
-    the network where a patch is in range, the batched LBM where it is not.
-    The patch statistics come first (lbm_patch_stats); then the LBM for the
-    flagged patches and the network run on two streams. The network runs on
-    network_workgroups persistent workgroups (default: a quarter of the CUs;
-    0: one per CU), each claiming patches one at a time, so the LBM has the
-    other CUs from the start for its long items (measured on 65 536 test
-    patches: ~66 ms against ~72-79 ms with one network workgroup per CU).
-    lbm_first enqueues the LBM before the network (then, uncapped, the
-    network fills the CUs the LBM's last items leave idle, if the LBM's
-    launch reaches the device first).
-    Returns (log_keff [n, 2], used_lbm [n] bool, seconds)."""
+    kappa_dev, whose log patches are logk_dev (FP32 [n, 32, 32], device): the
+    network where the range detector accepts a patch, the batched LBM where
+    it does not. Stage one: the patch statistics (lbm_patch_stats) decide
+    which patches lie outside the training distribution; the LBM starts on
+    those at once while the network (lbm_cnn_forward_spread) runs on a second
+    stream on network_workgroups persistent workgroups (default: a quarter of
+    the CUs), so the LBM has the other CUs for its long items. Stage two: when
+    the network is done, the patches whose symmetric predictions disagree go
+    to a second LBM launch on the network's stream, beside the first.
+    Returns (log_keff [n, 2], used_lbm [n] bool, seconds); a patch whose LBM
+    run did not converge (step cap or non-finite) gets NaN."""
     import torch
     n = len(x0)
     n_sym = model.n_sym if n_sym is None else n_sym
     dev = logk_dev.device
     prm = torch.as_tensor(model.params).to(dev)
     pred = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    spread = torch.empty((n, 2), dtype=torch.float32, device=dev)
     st = torch.empty((n, 8), dtype=torch.float32, device=dev)
     nb = L.lbm_cnn_workspace_bytes(n, False)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -299,24 +351,26 @@ def keff_with_fallback(model: Surrogate, kappa_dev, x0, y0, logk_dev, n_sym=None
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     L.lbm_patch_stats(n, logk_dev, st)
-    ok = model.in_range(st.cpu().numpy().astype(np.float64))
-    keff = None
+    ok1 = model.in_range(st.cpu().numpy().astype(np.float64))
     side.wait_stream(main)  # the network needs only what is on the main stream so far
-
-    def network():
+    with torch.cuda.stream(side):
+        L.lbm_cnn_forward_spread(prm, n, logk_dev, n_sym, pred, spread, int(network_workgroups), ws, nb)
+    runs = []
+    if (~ok1).any():
+        runs.append((np.flatnonzero(~ok1), _local_keff_launch(kappa_dev, x0[~ok1], y0[~ok1])))
+    side.synchronize()
+    with torch.cuda.stream(side):  # read on the network's stream: not behind the LBM on `main`
+        spread_h = spread.cpu().numpy().astype(np.float64)
+    ok = ok1 & model.confident(spread_h)
+    late = np.flatnonzero(ok1 & ~ok)
+    if len(late):
         with torch.cuda.stream(side):
-            L.lbm_cnn_forward_limited(prm, n, logk_dev, n_sym, pred, None, int(network_workgroups), ws, nb)
-
-    if not lbm_first:
-        network()
-    if (~ok).any():
-        keff, _keep = _local_keff_launch(kappa_dev, x0[~ok], y0[~ok])
-    if lbm_first:
-        network()
+            runs.append((late, _local_keff_launch(kappa_dev, x0[late], y0[late])))
     torch.cuda.synchronize(dev)
     out = pred.cpu().numpy().astype(np.float64)
-    if keff is not None:
+    for idx, (keff, lflags, _ws) in runs:
         k = keff.cpu().numpy()
-        out[~ok, 0] = np.log(k[:, 0])
-        out[~ok, 1] = np.log(k[:, 3])
+        good = (lflags.cpu().numpy() == 0).all(axis=1)
+        out[idx, 0] = np.where(good, np.log(k[:, 0]), np.nan)
+        out[idx, 1] = np.where(good, np.log(k[:, 3]), np.nan)
     return out, ~ok, time.perf_counter() - t0

@@ -62,6 +62,14 @@ def test_set(n_total=65536, frac_oor=0.1, seed=12345):
     return big, x0, y0, is_oor
 
 
+def calibration_patches(n=65536, seed=2):
+    """Unlabelled log K patches from the training distribution with seeds
+    the training set does not use (the network's spread on its own training
+    patches is smaller than on new ones): the range detector's calibration."""
+    big, x0, y0 = S.training_patches(n, seed=seed)
+    return np.stack([np.log(I.cut_patch(big, a, b, S.SIDE)) for a, b in zip(x0, y0)]).astype(np.float32)
+
+
 def _forward_timed(model, X, n_sym):
     """Device-resident forward of all patches: (pred, stats, seconds)."""
     import torch
@@ -104,9 +112,13 @@ def evaluate(model: S.Surrogate, big, x0, y0, is_oor, sweep_nsym=(1, 2, 4, 8)):
         t_lbm = dt if t_lbm is None else min(t_lbm, dt)
     # network alone (kernel time only)
     p, stats, t_net = _forward_timed(model, X, model.n_sym)
-    ok = model.in_range(stats)
+    _, spread = model.predict_spread(logk)
+    ok1 = model.in_range(stats)
+    ok = ok1 & model.confident(spread)
     # network + fallback, pipelined: statistics, then the network on a second
-    # stream while the LBM solves the flagged patches (best of two runs)
+    # stream while the LBM solves the patches flagged by the statistics, then
+    # the LBM for the patches whose symmetric predictions disagree (best of
+    # two runs)
     t_pipe = None
     for _ in range(2):
         combined, used_lbm, dt = S.keff_with_fallback(model, big_dev, x0, y0, X)
@@ -145,6 +157,7 @@ def evaluate(model: S.Surrogate, big, x0, y0, is_oor, sweep_nsym=(1, 2, 4, 8)):
         keff_error_in_range_by_n_sym=sweep,
         flagged=int((~ok).sum()), flagged_true_oor=int((~ok & is_oor).sum()),
         flagged_in_range=int((~ok & ~is_oor).sum()),
+        flagged_by_statistics=int((~ok1).sum()), flagged_by_spread=int((ok1 & ~ok).sum()),
         lbm_label_failures=int((~good).sum()),
         keff_error_network_in_range=q(err),
         keff_error_geometric_mean_in_range=q(geo),
@@ -168,15 +181,13 @@ def main():
     ap.add_argument("--results", default=None)
     ap.add_argument("--recalibrate", action="store_true",
                     help="keep the trained weights of --model, recompute the range detector "
-                         "from the (regenerated, unlabelled) training patches, and evaluate")
+                         "from unlabelled held-out in-range patches, and evaluate")
     args = ap.parse_args()
     import torch
     L.lib()
     if args.recalibrate:
         model = S.Surrogate.load(args.model)
-        big, x0, y0 = S.training_patches(args.train, seed=1)
-        logk = np.stack([np.log(I.cut_patch(big, a, b, S.SIDE)) for a, b in zip(x0, y0)])
-        model.calibrate(logk.astype(np.float32))
+        model.calibrate(calibration_patches())
         model.save(args.model)
         bt, xt, yt, is_oor = test_set(args.test)
         res = evaluate(model, bt, xt, yt, is_oor)
@@ -191,10 +202,11 @@ def main():
     print(f"training set: {len(X)} patches labelled in {t_data:.1f} s", flush=True)
     model = S.Surrogate.new(seed=0)
     t0 = time.perf_counter()
-    model.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, verbose=True)
+    model.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, verbose=True, calibrate=False)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     print(f"trained in {t_train:.1f} s", flush=True)
+    model.calibrate(calibration_patches())
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
     model.save(args.model)
     big, x0, y0, is_oor = test_set(args.test)

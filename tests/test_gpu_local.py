@@ -176,30 +176,146 @@ def test_local_flags_step_cap_and_bad_kappa(L):
     assert (res.steps[1] == 20).all()
 
 
+def _check_strict(keff_g, keff_o):
+    """Each diagonal entry within KEFF_TOL of its own oracle value (a nearly
+    blocked direction is held to its own size, not to the open one's), the
+    off-diagonal entries within KEFF_TOL of the larger diagonal entry."""
+    scale = max(abs(keff_o[0]), abs(keff_o[3]))
+    e_diag = max(abs(keff_g[0] / keff_o[0] - 1), abs(keff_g[3] / keff_o[3] - 1))
+    e_off = max(abs(keff_g[1] - keff_o[1]), abs(keff_g[2] - keff_o[2])) / scale
+    assert e_diag < KEFF_TOL and e_off < KEFF_TOL, (keff_g, keff_o, e_diag, e_off)
+    return max(e_diag, e_off)
+
+
+def _oracle_keff_many(field, x0, y0, sides, threads=16):
+    """Oracle K_eff of many patches by its time stepping to a relative change
+    of 1e-10 per 100 steps (within ~1e-8 of the fixed point even for the
+    slowest items here), items spread over host threads, one oracle call per
+    thread, each single-threaded."""
+    import concurrent.futures as cf
+
+    def one(args):
+        O.set_threads(1)
+        x, y, s = args
+        r = O.local_keff(I.cut_patch(field, x, y, s), TAU, EPS, NU, G, check_every=100, tol=1e-10,
+                         max_steps=2_000_000)
+        assert (r.status == 0).all(), (x, y, s, r.status)
+        return r.keff
+
+    O.lib()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        return np.array(list(ex.map(one, [(int(a), int(b), int(c)) for a, b, c in zip(x0, y0, sides)])))
+
+
+def _full_size_sample(field, steps, patches, n_random, rng):
+    """Indices: the 32 slowest items (most steps over both drives), the 32
+    with the largest spread of ln kappa, and n_random others; patches:
+    (x0, y0, side) per item."""
+    sd = np.array([np.log(I.cut_patch(field, *a)).std() for a in patches])
+    slow = np.argsort(steps.max(axis=1))[-32:]
+    het = np.argsort(sd)[-32:]
+    rest = np.setdiff1d(np.arange(len(steps)), np.union1d(slow, het))
+    return np.union1d(np.union1d(slow, het), rng.choice(rest, n_random, replace=False))
+
+
 def test_local_full_size_sampled(L):
     """The 2048 x 2048 field (sigma 1.5, correlation length 32) cut into the
     4096 tiles of 32 x 32 plus 4096 mixed patches with sides from
-    {16, 24, 32, 48, 64}, each set in one persistent launch (the benchmark's
-    configuration), with sampled items checked against the oracle."""
+    {16, 24, 32, 48, 64}, each set in one call (the benchmark's
+    configuration: FP32 state, rebased, no FP64 re-run), with at least 256
+    items of each set checked against the oracle, every diagonal entry
+    against its own value: the slowest, the most heterogeneous and a random
+    sample."""
     w = I.workload_fine(seed=1)
     field = w["kappa"]
     kdev = torch.as_tensor(field).cuda()
     xt, yt, st = I.tile_patches(2048, 2048, 32)
-    rt = L.local_keff(None, xt, yt, st, TAU, EPS, NU, G, tol=GPU_TOL, kappa_dev=kdev)
+    rt = L.local_keff(None, xt, yt, st, TAU, EPS, NU, G, tol=GPU_TOL, kappa_dev=kdev,
+                      max_steps=400000)
     assert (rt.flags == 0).all(), np.unique(rt.flags, return_counts=True)
     xm, ym, sm = I.mixed_patches(4096, 2048, 2048, seed=1)
-    rm = L.local_keff(None, xm, ym, sm, TAU, EPS, NU, G, tol=GPU_TOL, kappa_dev=kdev)
+    rm = L.local_keff(None, xm, ym, sm, TAU, EPS, NU, G, tol=GPU_TOL, kappa_dev=kdev,
+                      max_steps=400000)
     assert (rm.flags == 0).all(), np.unique(rm.flags, return_counts=True)
     rng = np.random.default_rng(7)
-    for i in rng.choice(4096, 6, replace=False):
-        _check(rt.keff[i], _oracle_keff(field, xt[i], yt[i], 32))
-    by_side = {s: np.flatnonzero(sm == s) for s in (16, 24, 32, 48, 64)}
-    for s, idx in by_side.items():
-        i = idx[0]
-        _check(rm.keff[i], _oracle_keff(field, xm[i], ym[i], s, exact=False))
+    it = _full_size_sample(field, rt.steps, list(zip(xt, yt, st)), 200, rng)
+    assert len(it) >= 256
+    ko = _oracle_keff_many(field, xt[it], yt[it], st[it])
+    errs = [_check_strict(rt.keff[i], k) for i, k in zip(it, ko)]
+    print(f"tiles: {len(it)} items, max error {max(errs):.2e}")
+    im = _full_size_sample(field, rm.steps, list(zip(xm, ym, sm)), 200, rng)
+    assert len(im) >= 256 and set(np.unique(sm[im])) == {16, 24, 32, 48, 64}
+    ko = _oracle_keff_many(field, xm[im], ym[im], sm[im])
+    errs = [_check_strict(rm.keff[i], k) for i, k in zip(im, ko)]
+    print(f"mixed: {len(im)} items, max error {max(errs):.2e}")
     # every tensor is positive on the diagonal and finite
     assert np.isfinite(rt.keff).all() and (rt.keff[:, [0, 3]] > 0).all()
     assert np.isfinite(rm.keff).all() and (rm.keff[:, [0, 3]] > 0).all()
+
+
+def _slow_patches():
+    """32 x 32 patches where FP32 state is known to stop short of the fixed
+    point: the most permeable tiles of a sigma-2.5, l-32 field (in the
+    surrogate's training range), the most heterogeneous tiles of a sigma-3.5,
+    l-8 field and the most permeable tiles of a field with 8-row streaks of
+    K x 1e3 (the surrogate's out-of-range kinds). Returns (mosaic, x0, y0)."""
+    fields = [I.lognormal_kappa(256, 256, 2.5, 32.0, 101),
+              I.lognormal_kappa(256, 256, 3.5, 8.0, 102),
+              I.channelize(I.lognormal_kappa(256, 256, 1.0, 8.0, 103), 0.25, 8, 1e3, 103)]
+    picks = []
+    for f, key in zip(fields, ("mean", "sd", "mean")):
+        t = I.log_patches(f, 32)
+        score = np.exp(t).mean(axis=(1, 2)) if key == "mean" else t.std(axis=(1, 2))
+        picks.append(np.argsort(score)[-6:])
+    big = np.concatenate(fields, axis=1)
+    x0, y0 = [], []
+    for j, idx in enumerate(picks):
+        for i in idx:
+            x0.append(256 * j + 32 * (i % 8))
+            y0.append(32 * (i // 8))
+    return big, np.array(x0, np.int32), np.array(y0, np.int32)
+
+
+def test_local_f32_permeable_and_heterogeneous_items(L):
+    """FP32 state on the slowest kinds of patch against the oracle's exact
+    fixed point (Sec. 3, Eq. tensor-kappa). Permeable patches (relaxation
+    time kappa / (eps nu), 20 000 - 150 000 steps) stopped short by 1-3e-4
+    when the FP32 state held plain deviations; stored rebased on the mean
+    momentum they meet 1e-4 on every diagonal entry. The very heterogeneous
+    patches (sigma 3.5) meet 1e-4 relative to the tensor's largest entry,
+    and with an FP32 step budget (slow items re-run with FP64 state) on
+    every diagonal entry; the re-run gives what FP64 state from the start
+    gives."""
+    big, x0, y0 = _slow_patches()
+    side = np.full(len(x0), 32, np.int32)
+    r = L.local_keff(big, x0, y0, side, TAU, EPS, NU, G, tol=GPU_TOL, max_steps=400000,
+                     fp32_step_budget=0)
+    assert (r.flags == 0).all(), r.flags
+    ko = [DS.keff_direct(I.cut_patch(big, x0[i], y0[i], 32), TAU, EPS, NU, G) for i in range(len(x0))]
+    het = np.zeros(len(x0), bool)
+    het[6:12] = True  # the sigma-3.5 tiles of _slow_patches
+    errs = []
+    for i in range(len(x0)):
+        errs.append(_check(r.keff[i], ko[i]) if het[i] else _check_strict(r.keff[i], ko[i]))
+    print(f"no budget: max error {max(errs):.2e} over {len(x0)} patches; steps max {r.steps.max()}")
+    budget = 10000
+    rb = L.local_keff(big, x0, y0, side, TAU, EPS, NU, G, tol=GPU_TOL, max_steps=400000,
+                      fp32_step_budget=budget)
+    assert (rb.flags == 0).all(), rb.flags
+    assert (rb.steps > budget).any()  # some items took the FP64 re-run
+    errs = [_check_strict(rb.keff[i], ko[i]) for i in range(len(x0))]
+    print(f"budget {budget}: max error {max(errs):.2e}")
+    slow = np.flatnonzero((rb.steps > budget).any(axis=1))
+    r64 = L.local_keff(big, x0[slow], y0[slow], side[slow], TAU, EPS, NU, G, tol=GPU_TOL,
+                       max_steps=400000, pop_dtype=L.LBM_F64)
+    for j, i in enumerate(slow):
+        for d in (0, 1):
+            if rb.steps[i, d] > budget:
+                # same FP64 arithmetic per cell; only the order of the mean's
+                # partial sums differs with the thread layout
+                assert abs(int(rb.steps[i, d]) - int(r64.steps[j, d])) <= 100
+                cols = [0, 2] if d == 0 else [1, 3]
+                assert np.allclose(rb.keff[i, cols], r64.keff[j, cols], rtol=1e-9, atol=0)
 
 
 def test_local_f64_state_reaches_fixed_point_where_f32_stalls(L):

@@ -109,6 +109,42 @@ def test_symmetric_forward_matches_oracle(L, n_sym):
     assert np.sqrt((err ** 2).sum() / (pred_o ** 2).sum()) < 5e-3
 
 
+@pytest.mark.parametrize("n_sym", [1, 2, 5])
+def test_forward_spread_matches_oracle(L, n_sym):
+    """lbm_cnn_forward_spread: the same mean prediction as lbm_cnn_forward
+    (bit for bit), and for each output the range (largest minus smallest) of
+    the n_sym symmetric predictions, against the oracle's per-symmetry
+    predictions mapped back to the patch's axes."""
+    p = _params(15)
+    x = _patches(23, 16)
+    per = []
+    for sym in range(n_sym):
+        y, c = C.forward(p, C.transform(x, sym))
+        q = y + c["m"][:, None]
+        per.append(q[:, ::-1] if sym & 1 else q)
+    per = np.stack(per)
+    spread_o = per.max(axis=0) - per.min(axis=0)
+    prm = torch.tensor(_flat(p), device="cuda")
+    xd = torch.tensor(x.astype(np.float32), device="cuda")
+    pred = torch.empty((23, 2), dtype=torch.float32, device="cuda")
+    ref = torch.empty_like(pred)
+    spr = torch.empty_like(pred)
+    nb = L.lbm_cnn_workspace_bytes(23, False)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    L.lbm_cnn_forward_spread(prm, 23, xd, n_sym, pred, spr, 7, ws, nb)
+    L.lbm_cnn_forward(prm, 23, xd, n_sym, ref, None, ws, nb)
+    torch.cuda.synchronize()
+    assert torch.equal(pred, ref)
+    spr = spr.cpu().numpy()
+    if n_sym == 1:
+        assert (spr == 0).all()
+    else:
+        assert np.abs(spr - spread_o).max() < 2e-2 * (1 + np.abs(per).max()), np.abs(spr - spread_o).max()
+        assert (spr >= 0).all()
+    with pytest.raises(L.LbmError):
+        L.lbm_cnn_forward_spread(prm, 23, xd, n_sym, pred, None, 0, ws, nb)
+
+
 def test_symmetric_forward_is_equivariant_on_gpu(L):
     """With all eight symmetries averaged, a transformed patch reads exactly the
     same eight pixel arrangements as the original, so predictions agree up to
@@ -284,8 +320,10 @@ def test_forward_with_fewer_workgroups_is_identical(L):
 
 def test_pipelined_fallback_matches_separate_paths(L):
     """keff_with_fallback (statistics, then the network on a second stream
-    concurrent with the LBM on the flagged patches) returns the network's
-    prediction where in range and the LBM's elsewhere."""
+    concurrent with the LBM on the patches the statistics flag, then the LBM
+    on the patches whose symmetric predictions disagree) returns the
+    network's prediction where both stages accept a patch and the LBM's
+    elsewhere, whatever the cap on the network's workgroups."""
     from paper_1312_0195_amd import surrogate as S
     from paper_1312_0195_amd import train_surrogate as T
     model = S.Surrogate.load(T.DEFAULT_MODEL)
@@ -294,12 +332,15 @@ def test_pipelined_fallback_matches_separate_paths(L):
     logk = np.stack([np.log(I.cut_patch(big, a, b, 32)) for a, b in zip(x0, y0)]).astype(np.float32)
     xd = torch.as_tensor(logk).cuda()
     pred, stats = model.predict(logk)
-    ok = model.in_range(stats)
+    pred2, spread = model.predict_spread(logk)
+    assert np.array_equal(pred, pred2)
+    ok1 = model.in_range(stats)
+    ok = ok1 & model.confident(spread)
+    assert (~ok1).any() and (ok1 & ~ok).any() and ok.any()  # both stages flag something here
     y_lbm, _ = S.label_patches(None, x0[~ok], y0[~ok], kappa_dev=kd)
-    for lbm_first, wg in ((True, 0), (False, 0), (False, 96)):  # launch order and cap: same results
-        out, used, secs = S.keff_with_fallback(model, kd, x0, y0, xd, lbm_first=lbm_first,
-                                               network_workgroups=wg)
-        assert (used == ~ok).all() and used.any() and (~used).any()
+    for wg in (0, 96, None):
+        out, used, secs = S.keff_with_fallback(model, kd, x0, y0, xd, network_workgroups=wg)
+        assert (used == ~ok).all()
         assert np.array_equal(out[ok], pred[ok])
         assert np.allclose(out[~ok], y_lbm, rtol=0, atol=1e-12)
         assert secs > 0
@@ -312,17 +353,21 @@ def test_trained_network_gains_over_the_method_without_it(L):
     method without the local problems (the block geometric mean of kappa as
     K_eff) it is far more accurate; (2) against the method without the
     network (the batched LBM for every patch) the network plus LBM fallback
-    is faster, at the accuracy the surrogate path is specified for (2%)."""
+    is faster, at the accuracy the surrogate path is specified for: K_eff
+    within 2% at the 95th percentile, in range and over all patches."""
     from paper_1312_0195_amd import surrogate as S
     from paper_1312_0195_amd import train_surrogate as T
     model = S.Surrogate.load(T.DEFAULT_MODEL)
     big, x0, y0, kind = T.test_set(16384)
     r = T.evaluate(model, big, x0, y0, kind, sweep_nsym=(model.n_sym,))
     net, geo = r["keff_error_network_in_range"], r["keff_error_geometric_mean_in_range"]
+    allp = r["keff_error_combined_all"]
+    print({k: r[k] for k in ("flagged", "flagged_true_oor", "flagged_in_range", "flagged_by_statistics",
+                              "flagged_by_spread")}, net, allp)
     assert r["lbm_label_failures"] == 0
-    assert net["p50"] < 0.01 and net["p95"] < 0.025, net
+    assert net["p50"] < 0.005 and net["p95"] <= 0.02, net
     assert net["p50"] < geo["p50"] / 10 and net["p95"] < geo["p95"] / 10, (net, geo)
-    assert r["keff_error_combined_all"]["p95"] < 0.05, r["keff_error_combined_all"]
+    assert allp["p95"] <= 0.02 and allp["p99"] <= 0.05, allp
     speedup = r["patches_per_s_network_plus_fallback"] / r["patches_per_s_lbm_only"]
     assert speedup > 1.5, (speedup, r["patches_per_s_network_plus_fallback"], r["patches_per_s_lbm_only"])
 
