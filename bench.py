@@ -392,6 +392,75 @@ def bench_d3q19(L, torch, n=256, steps=200, warmup=20):
                     D3Q19_BYTES_PER_LU * cells / (us * 1e-6) / 1e9 / copy_gbs, 4))
 
 
+def bench_upscale_reduced(L, torch, n=512, r=64):
+    """The upscaling workload (log-normal K, sigma 2, correlation length
+    64 n / 4096, fully periodic) at the reduced size n = 512 with r = 64:
+    local problems, coarse solve (tensor K_eff) and the fine grid to steady
+    state (relative change 1e-6 per check, the coarse check every 100 steps
+    and the fine one every 100 r: the same physical time), with the oracle
+    timed beside it."""
+    from paper_1312_0195_amd import inputs as I
+    from paper_1312_0195_amd import upscale as U
+    kappa = I.workload_upscale(seed=1, n=n)["kappa"]
+    res = U.run(kappa, r, fine_tol=1e-6, fine_check=100 * r, coarse_tol=1e-6, coarse_check=100)
+    out = dict(workload=f"{n}x{n}, sigma 2, corr {64 * n // 4096}, periodic, r {r}",
+               rel_l2_tensor=round(res.rel_l2, 5), rel_l2_scalar=round(res.rel_l2_scalar, 5),
+               t_local_s=round(res.t_local, 5), t_coarse_s=round(res.t_coarse, 5),
+               t_fine_s=round(res.t_fine, 4), fine_steps=int(res.fine_steps),
+               coarse_steps=int(res.coarse_steps),
+               speedup_upscaled_vs_fine=round(res.t_fine / (res.t_local + res.t_coarse), 2))
+    return out, kappa, res
+
+
+def cpu_baseline_upscale(kappa, res, r=64, fine_sample_steps=200):
+    """The oracle on the reduced upscaling workload: all local problems (items
+    over host threads, each single-threaded; Sec. 3, Eq. tensor-kappa), the
+    coarse solve with the tensor drag on the coarse lattice (Sec. 3 mapping),
+    and the fine step timed on a bounded sample of steps, its time to the
+    GPU run's steady-state step count projected from that rate."""
+    import concurrent.futures as cf
+    from oracle import oracle as O
+    from paper_1312_0195_amd import inputs as I
+    n = kappa.shape[0]
+    nc = n // r
+    threads = min(os.cpu_count() or 1, 16)
+    main_threads = O.num_threads()
+
+    def solve(ij):
+        O.set_threads(1)
+        J, Ii = ij
+        return O.local_keff(kappa[J * r:(J + 1) * r, Ii * r:(Ii + 1) * r], 0.8, 0.4, 0.1, 1e-6,
+                            check_every=100, tol=1e-7, max_steps=2_000_000).keff
+
+    O.lib()
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        keff = np.array(list(ex.map(solve, [(J, Ii) for J in range(nc) for Ii in range(nc)])))
+    t_local = time.perf_counter() - t0
+    O.set_threads(main_threads)
+    # coarse lattice: dx, dt x r; kappa / r^2, G x r, nu / r, tau_c = 1/2 + (tau - 1/2) / r
+    pf = O.Params(nx=n, ny=n, tau=0.8, eps=0.4, nu=0.1)
+    pc, sc = O.coarse_params(pf, r)
+    pc = O.Params(nx=pc.nx, ny=pc.ny, tau=pc.tau, eps=pc.eps, nu=pc.nu, perm_kind=4)
+    kt = (keff * sc["kappa"]).reshape(nc, nc, 4)
+    t0 = time.perf_counter()
+    rc = O.run(pc, kt, (1e-6 * sc["force"], 0.0), max_steps=4_000_000, check_every=100, tol=1e-6)
+    t_coarse = time.perf_counter() - t0
+    pfine = O.Params(nx=n, ny=n, tau=0.8, eps=0.4, nu=0.1)
+    t0 = time.perf_counter()
+    O.run(pfine, kappa, (1e-6, 0.0), max_steps=fine_sample_steps)
+    dt = time.perf_counter() - t0
+    mlups = n * n * fine_sample_steps / dt / 1e6
+    return dict(kind="oracle", cores=threads, cpu_model=_cpu_model(),
+                t_local_s=round(t_local, 3), local_items=int(nc * nc * 2),
+                t_coarse_s=round(t_coarse, 4), coarse_steps=int(rc.steps),
+                fine_mlups=round(mlups, 1),
+                fine_sample=f"{fine_sample_steps} steps of {n}x{n}, {dt:.1f} s, {O.num_threads()} threads",
+                t_fine_projected_s=round(res.fine_steps * n * n / (mlups * 1e6), 1),
+                keff_max_rel_diff_vs_gpu=float(np.max(np.abs(keff - res.keff.reshape(-1, 4))) /
+                                               np.max(np.abs(keff[:, [0, 3]]))))
+
+
 def bench_seeds(L, torch, steps, no_local, seeds=(2, 3)):
     """The fine step and the local problems on the same workloads drawn with
     other seeds (the headline numbers use seed 1): fine MLUPS over `steps`
@@ -462,6 +531,7 @@ def main():
     ap.add_argument("--no-local", action="store_true")
     ap.add_argument("--no-d3q19", action="store_true")
     ap.add_argument("--no-seeds", action="store_true", help="skip the seed 2 and 3 workloads")
+    ap.add_argument("--no-upscale", action="store_true", help="skip the reduced upscaling leg")
     ap.add_argument("--no-paper-timing", action="store_true",
                     help="skip the 100 x 100 Sec. 4.1 leg (its 200000 steps swamp a profile)")
     ap.add_argument("--only-d3q19", action="store_true",
@@ -528,7 +598,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                      "traffic": traffic,
-                     "kernel": f"k_stepd<float, walls, scalar, {DEPTH}> ({DEPTH} time steps per launch)",
+                     "kernel": f"k_stepd<float, walls, scalar, no force field, {DEPTH}, double> ({DEPTH} time steps per launch, FP64 arithmetic)",
                      "avg_launch_us": round(step_ms * 1e3, 3),
                      "launches_timed": KERNEL_LAUNCHES,
                      "warmup_launches": KERNEL_WARMUP_LAUNCHES,
@@ -554,6 +624,10 @@ def main():
         del kd
         if not args.no_cpu:
             result["local_keff"]["cpu_baseline"] = cpu_baseline_local(kappa)
+    if not args.no_local and not args.no_upscale:
+        result["upscale_reduced"], kap_u, res_u = bench_upscale_reduced(L, torch)
+        if not args.no_cpu:
+            result["upscale_reduced"]["cpu_baseline"] = cpu_baseline_upscale(kap_u, res_u)
     if not args.no_seeds:
         result["seeds"] = bench_seeds(L, torch, min(args.steps, 6000), args.no_local)
     if not args.no_surrogate and not args.no_local:
