@@ -368,3 +368,47 @@ def test_paper_sec41_transient_matches_oracle(L, scheme):
     # the density: 5000 steps of rounding (the GPU keeps deviations from rho0,
     # the oracle full populations) at tau 0.53, where sound waves barely decay
     assert np.abs(rho.cpu().numpy() - rho_o).max() < 5e-12
+
+
+def test_fine_f32_arithmetic_mode(L):
+    """LBM_F32_FAST (FP32 state and FP32 collision arithmetic, the drag as its
+    deficit): multi-step launches bit-identical to single steps, and against
+    the oracle over the 20000 steps of the fine workload on a 128 x 128 field
+    of the same statistics: within 2e-4 in relative L2 of the velocity (the
+    default FP64 arithmetic is within 1e-5; the 2048^2 run measured 6.5e-5)."""
+    nx = ny = 128
+    k = I.lognormal_kappa(nx, ny, 1.5, 8.0, seed=2)
+    g = (1e-6, 0.0)
+    u_o, _, _ = _oracle_run(nx, ny, k, 0.8, 0.4, 0.1, g, 1, 20000)
+    u_g, _, _, _ = _gpu_run(L, nx, ny, k, 0.8, 0.4, 0.1, g, 1, 20000, L.LBM_F32_FAST)
+    err = np.sqrt(np.sum((u_g - u_o) ** 2) / np.sum(u_o ** 2))
+    assert err < 2e-4, err
+    p = L.make_params(150, 45, 0.7, 0.4, 0.1, 1.0, 1e-6, 3e-7, 1, L.LBM_F32_FAST)
+    kk = I.lognormal_kappa(150, 45, 1.5, 6.0, seed=11)
+    a, b = L.FineSolver(p, kk), L.FineSolver(p, kk)
+    a.step(29)
+    for _ in range(29):
+        b.step(1)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    with pytest.raises(L.LbmError):   # the Guo form runs in FP64 arithmetic only
+        L.FineSolver(L.make_params(16, 16, 0.8, 0.4, 0.1, 1.0, 1e-6, 0.0, 1, L.LBM_F32_FAST,
+                                   L.LBM_PERM_SCALAR, L.LBM_SCHEME_GUO), np.ones((16, 16)))
+
+
+@pytest.mark.parametrize("ratio", [50.0, 100.0])
+def test_table3_refined_cell_matches_oracle(L, golden, ratio):
+    """Table 3's refined checkerboard (Sec. 4.2.2: squares of 100 points,
+    dx 1e-3 m, dt 1e-5 s, tau 1/2): the 200 x 200 periodic cell run to steady
+    state with FP64 state against the oracle's exact fixed point (stored by
+    tests/golden/make_table3_1000.py) at 1e-7."""
+    U = I.LatticeUnits(dx=1e-3, dt=1e-5)
+    field = I.checkerboard_field(1000, 10, 1e-12, ratio * 1e-12)[:200, :200].copy()
+    g, nu = float(U.force(2.0)), U.nu(2e-6)
+    p = L.make_params(200, 200, 0.5, 0.8, nu, 1.0, g, 0.0, 0, L.LBM_F64)
+    s = L.FineSolver(p, U.kappa(field))
+    st, done, mu = s.step(2_000_000, 1e-12, 10000)
+    s.close()
+    assert st == L.LBM_OK, (st, done)
+    kxx = float(U.kappa_to_phys(nu * mu[0] / g)) / 1e-12
+    want = {float(r): float(k) for r, k, _ in golden("table3_1000_oracle.txt")}[ratio]
+    assert kxx == pytest.approx(want, rel=1e-7), (kxx, want)
