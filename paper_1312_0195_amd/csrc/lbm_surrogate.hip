@@ -24,7 +24,8 @@
 // conv2-4 weights to BF16 in the two layouts the MFMA operands need.
 //
 // Forward: one workgroup (8 waves) per patch at a time, persistent over the
-// batch. Activations stay in LDS ([pixel][channel] BF16, 64 KB per layer,
+// batch. Activations stay in LDS ([pixel][channel] BF16 with the channel
+// chunks of each pixel permuted (act_off), 64 KB per layer,
 // two buffers); a 16x16x32 MFMA takes 16 pixels x 32 input channels of one
 // tap, so a 3x3 layer is 9 MFMAs per 16-pixel x 16-channel output tile. The
 // last conv layer is pooled straight from the accumulators.
@@ -80,6 +81,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int wrap32(int v) { return v & (kSide - 1); }
+
+// Element offset of the 8-channel chunk c (0..3) of pixel p in an activation
+// buffer of the forward pass in LDS. The four 16-byte chunks of a pixel are
+// permuted by (p >> 1) & 3: the layers read one chunk of 16 consecutive
+// pixels per MFMA operand (one 16-byte read per lane), and without the
+// permutation those reads, 64 bytes apart, fall on the same few banks. With
+// it, any 8 consecutive pixels (also across the periodic wrap of a row) hit
+// 8 different 16-byte bank groups. Global copies of the activations keep the
+// plain [pixel][channel] order.
+__device__ __forceinline__ int act_off(int p, int c) { return p * kC + ((c ^ ((p >> 1) & 3)) << 3); }
 __device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
 __device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
 
@@ -197,7 +208,8 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
                                            const float *__restrict__ prm, __bf16 *__restrict__ gout)
 {
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = lane & 15, g = lane >> 4;  // n: output channel row of A / pixel of B; g: k-group
     bf16x8 w0, w1;
 #pragma unroll
@@ -212,28 +224,36 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
         b0[i] = prm[oB1 + g * 4 + i];
         b1[i] = prm[oB1 + 16 + g * 4 + i];
     }
+    // Every tile of this wave has the same column half (kWaves is even), so
+    // the offset of tap j from the tile's row start, wrapped in x, is fixed
+    // per lane; the row wrap is the wrap of the whole 1024-pixel plane.
+    // Padded taps (t >= 9) read the centre pixel; their weights are zero.
+    static_assert(kWaves % 2 == 0, "the column half of a wave's tiles must not change");
+    const int x0 = (wave & 1) * 16;
+    int off[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int t = g * 8 + j;
+        const int tt = t < 9 ? t : 4;
+        off[j] = tap_dy(tt) * kSide + wrap32(x0 + n + tap_dx(tt));
+    }
     for (int tile = wave; tile < kPix / 16; tile += kWaves) {
-        const int y = tile >> 1, x0 = (tile & 1) * 16;
+        const int ybase = (tile >> 1) * kSide;
         bf16x8 a;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int t = g * 8 + j;
-            const int tt = t < 9 ? t : 4;  // padded taps read any pixel and are zeroed
-            const float v = xs[wrap32(y + tap_dy(tt)) * kSide + wrap32(x0 + n + tap_dx(tt))];
-            a[j] = (__bf16)(t < 9 ? v : 0.0f);
-        }
+        for (int j = 0; j < 8; ++j) a[j] = (__bf16)xs[(ybase + off[j]) & (kPix - 1)];
         const f32x4 z = {0.f, 0.f, 0.f, 0.f};
         const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, a, z, 0, 0, 0);
         const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, a, z, 0, 0, 0);
-        const int p = y * kSide + x0 + n;  // D column = pixel
+        const int p = ybase + x0 + n;  // D column = pixel
         bf16x4 v0, v1;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             v0[i] = (__bf16)fmaxf(acc0[i] + b0[i], 0.0f);
             v1[i] = (__bf16)fmaxf(acc1[i] + b1[i], 0.0f);
         }
-        *reinterpret_cast<bf16x4 *>(out + p * kC + g * 4) = v0;
-        *reinterpret_cast<bf16x4 *>(out + p * kC + 16 + g * 4) = v1;
+        *reinterpret_cast<bf16x4 *>(out + act_off(p, g >> 1) + (g & 1) * 4) = v0;
+        *reinterpret_cast<bf16x4 *>(out + act_off(p, 2 + (g >> 1)) + (g & 1) * 4) = v1;
         if (gout) {
             *reinterpret_cast<bf16x4 *>(gout + p * kC + g * 4) = v0;
             *reinterpret_cast<bf16x4 *>(gout + p * kC + 16 + g * 4) = v1;
@@ -272,46 +292,72 @@ struct FwdArgs {
     int *next;              // patches claimed beyond the first gridDim.x (zeroed by k_pack)
 };
 
-// One 3x3, 32 -> 32 layer on MFMA. in/out are [pixel][channel] BF16 in LDS.
-// The product is D[co][pixel] = W[co][ci] X[ci][pixel] per tap (A: weights,
-// held in registers; B: 8 channels of one pixel per lane, one 16-byte LDS
-// read), so each lane ends with 4 consecutive output channels of one pixel
-// and stores them with one 8-byte write. Each wave takes two 16-pixel tiles
-// at a time: four independent accumulation chains per tap. With POOL the
-// ReLU outputs are summed per channel into pool_part[wave][32] instead of
-// being stored. Not inlined: inlined into k_forward, its ~200 live registers
-// (weights of the nine taps, prefetched operands) spilled to scratch; as a
-// call the layer has the register file to itself (measured 1.14 x faster).
+// One 3x3, 32 -> 32 layer on MFMA. in/out are [pixel][channel] BF16 in LDS
+// (chunks permuted, act_off). The product is D[co][pixel] = W[co][ci]
+// X[ci][pixel] per tap (A: weights, held in registers; B: 8 channels of one
+// pixel per lane, one 16-byte LDS read), so each lane ends with 4
+// consecutive output channels of one pixel and stores them with one 8-byte
+// write. Each wave takes two 16-pixel tiles at a time: four independent
+// accumulation chains per tap. With POOL the ReLU outputs are summed per
+// channel into pool_part[wave][32] instead of being stored. Not inlined:
+// inlined into k_forward, its ~200 live registers (weights of the nine
+// taps, prefetched operands) spilled to scratch; as a call the layer has the
+// register file to itself (measured 1.14 x faster).
+// Address-space-qualified element types: a generic pointer makes the
+// compiler emit flat memory instructions, which count against the LDS wait
+// counter too, so every MFMA would wait for all LDS reads in flight.
+typedef __attribute__((address_space(3))) __bf16 lds_bf16;     // LDS (32-bit addresses)
+typedef __attribute__((address_space(1))) __bf16 glb_bf16;     // global memory
+typedef __attribute__((address_space(1))) const float glb_f32;
+
 template <bool POOL>
-__device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ in, __bf16 *__restrict__ out,
+__device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ in_p, __bf16 *__restrict__ out_p,
                                                     const __bf16 *__restrict__ wfl,
                                                     const float *__restrict__ bias,
-                                                    __bf16 *__restrict__ gout, float *pool_part)
+                                                    __bf16 *__restrict__ gout_p, float *pool_part)
 {
     constexpr int U = 2;  // tiles per iteration
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
+    typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+    typedef __attribute__((address_space(1))) bf16x4 glb_bf16x4;
+    typedef __attribute__((address_space(1))) const bf16x8 glb_bf16x8;
+    const lds_bf16 *in = (const lds_bf16 *)in_p;
+    lds_bf16 *out = (lds_bf16 *)out_p;
+    glb_bf16 *gout = (glb_bf16 *)gout_p;
+    const glb_bf16 *wg = (const glb_bf16 *)wfl;
+    glb_f32 *bg = (glb_f32 *)bias;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = lane & 15, g = lane >> 4;  // n: pixel within the tile (B, D) / co row (A); g: k-group
+    // Addressing: every tile of this wave has the same column half (kWaves is
+    // even), and the chunk permutation of act_off depends on the column only,
+    // so the column part of each tap's offset is fixed per lane (three
+    // values, dx = -1, 0, 1) and a tap's LDS offset is a wave-uniform row
+    // offset plus one of them.
+    static_assert(kWaves % 2 == 0, "the column half of a wave's tiles must not change");
+    const int x0 = (wave & 1) * 16;
+    int colp[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) colp[d] = act_off(wrap32(x0 + n + d - 1), g);
+    const int col0 = x0 + n;
+    const int op[2] = {act_off(col0, g >> 1) + (g & 1) * 4, act_off(col0, 2 + (g >> 1)) + (g & 1) * 4};
     bf16x8 w[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
-            w[t][ct] = *reinterpret_cast<const bf16x8 *>(wfl + (t * kC + ct * 16 + n) * kC + g * 8);
+            w[t][ct] = *reinterpret_cast<glb_bf16x8 *>(wg + (t * kC + ct * 16 + n) * kC + g * 8);
     float bb[2][4];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bb[ct][i] = bias[ct * 16 + g * 4 + i];
+        for (int i = 0; i < 4; ++i) bb[ct][i] = bg[ct * 16 + g * 4 + i];
     float ps[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     for (int tile = wave; tile < kPix / 16; tile += U * kWaves) {
-        int y[U], x0[U];
+        int y[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int tl = tile + u * kWaves;
-            y[u] = tl >> 1;
-            x0[u] = (tl & 1) * 16;
-        }
+        for (int u = 0; u < U; ++u) y[u] = (tile + u * kWaves) >> 1;
         f32x4 acc[U][2];
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -321,15 +367,15 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
         for (int t = 0; t < 9; ++t) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int p = wrap32(y[u] + tap_dy(t)) * kSide + wrap32(x0[u] + n + tap_dx(t));
-                const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(in + p * kC + g * 8);
+                const int rowp = wrap32(y[u] + tap_dy(t)) * (kSide * kC);
+                const bf16x8 xb = *reinterpret_cast<const lds_bf16x8 *>(in + rowp + colp[tap_dx(t) + 1]);
                 acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][0], xb, acc[u][0], 0, 0, 0);
                 acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][1], xb, acc[u][1], 0, 0, 0);
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int p = y[u] * kSide + x0[u] + n;  // D column = pixel
+            const int p = y[u] * kSide + col0;  // D column = pixel
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
                 bf16x4 v;
@@ -339,8 +385,8 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
                     if (POOL) ps[ct][i] += r;
                     v[i] = (__bf16)r;
                 }
-                if (!POOL) *reinterpret_cast<bf16x4 *>(out + p * kC + ct * 16 + g * 4) = v;
-                if (gout) *reinterpret_cast<bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
+                if (!POOL) *reinterpret_cast<lds_bf16x4 *>(out + y[u] * (kSide * kC) + op[ct]) = v;
+                if (gout) *reinterpret_cast<glb_bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
             }
         }
     }
