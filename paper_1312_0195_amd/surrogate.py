@@ -34,6 +34,14 @@ from . import lbm as L
 
 SIDE = 32
 PHYS = dict(tau=0.8, eps=0.4, nu=0.1, g=1e-6)
+# Quantile levels of the range detector's two thresholds over the in-range
+# calibration patches. Chosen on a validation set of the test recipe (another
+# seed): from (0.99, 0.95) to these, the K_eff error p95 over all patches grew
+# from 1.4% to 1.8% (p99 from 3.2% to 4.7%) and the pipelined path's time fell
+# by half there (5-8% on the test set). The time is set by the slowest
+# patches sent to the LBM, not by their number, and a slow patch that only
+# the spread stage flags starts after the network.
+Q_FEAT, Q_SPREAD = 0.998, 0.97
 
 
 def init_params(seed: int = 0) -> np.ndarray:
@@ -203,7 +211,7 @@ class Surrogate:
             self.calibrate(logk, device=device)
         return self
 
-    def calibrate(self, logk, q_feat=0.99, q_spread=0.95, device="cuda"):
+    def calibrate(self, logk, q_feat=Q_FEAT, q_spread=Q_SPREAD, device="cuda"):
         """Range detector from unlabelled in-range patches: the mean and
         covariance of the detector features, the q_feat quantile of their
         squared Mahalanobis distance, and the q_spread quantile of the spread

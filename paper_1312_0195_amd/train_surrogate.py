@@ -182,12 +182,16 @@ def main():
     ap.add_argument("--recalibrate", action="store_true",
                     help="keep the trained weights of --model, recompute the range detector "
                          "from unlabelled held-out in-range patches, and evaluate")
+    ap.add_argument("--q-feat", type=float, default=S.Q_FEAT,
+                    help="quantile of the in-range Mahalanobis distances kept by stage one")
+    ap.add_argument("--q-spread", type=float, default=S.Q_SPREAD,
+                    help="quantile of the in-range symmetric spreads kept by stage two")
     args = ap.parse_args()
     import torch
     L.lib()
     if args.recalibrate:
         model = S.Surrogate.load(args.model)
-        model.calibrate(calibration_patches())
+        model.calibrate(calibration_patches(), q_feat=args.q_feat, q_spread=args.q_spread)
         model.save(args.model)
         bt, xt, yt, is_oor = test_set(args.test)
         res = evaluate(model, bt, xt, yt, is_oor)
@@ -206,7 +210,7 @@ def main():
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     print(f"trained in {t_train:.1f} s", flush=True)
-    model.calibrate(calibration_patches())
+    model.calibrate(calibration_patches(), q_feat=args.q_feat, q_spread=args.q_spread)
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
     model.save(args.model)
     big, x0, y0, is_oor = test_set(args.test)
