@@ -91,6 +91,15 @@ __device__ __forceinline__ int wrap32(int v) { return v & (kSide - 1); }
 // 8 different 16-byte bank groups. Global copies of the activations keep the
 // plain [pixel][channel] order.
 __device__ __forceinline__ int act_off(int p, int c) { return p * kC + ((c ^ ((p >> 1) & 3)) << 3); }
+
+// The forward pass keeps one periodic halo row above and below each plane in
+// LDS (row -1 = row 31, row 32 = row 0): an activation buffer is 34 rows of
+// kSide * kC elements whose row 0 starts kSide * kC elements in (kActRow),
+// and the centred input plane has kSide floats before and after it. With
+// the halo a 3x3 stencil never wraps in y, so every operand read of a tile
+// is a per-lane base plus a compile-time offset.
+constexpr int kActRow = kSide * kC;               // elements per activation row
+constexpr int kActElems = (kSide + 2) * kActRow;  // one buffer with its halo rows
 __device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
 __device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
 
@@ -235,13 +244,13 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
     for (int j = 0; j < 8; ++j) {
         const int t = g * 8 + j;
         const int tt = t < 9 ? t : 4;
-        off[j] = tap_dy(tt) * kSide + wrap32(x0 + n + tap_dx(tt));
+        off[j] = tap_dy(tt) * kSide + wrap32(x0 + n + tap_dx(tt));  // rows -1 and 32 are xs's halo
     }
     for (int tile = wave; tile < kPix / 16; tile += kWaves) {
         const int ybase = (tile >> 1) * kSide;
         bf16x8 a;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = (__bf16)xs[(ybase + off[j]) & (kPix - 1)];
+        for (int j = 0; j < 8; ++j) a[j] = (__bf16)xs[ybase + off[j]];
         const f32x4 z = {0.f, 0.f, 0.f, 0.f};
         const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, a, z, 0, 0, 0);
         const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, a, z, 0, 0, 0);
@@ -254,6 +263,12 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
         }
         *reinterpret_cast<bf16x4 *>(out + act_off(p, g >> 1) + (g & 1) * 4) = v0;
         *reinterpret_cast<bf16x4 *>(out + act_off(p, 2 + (g >> 1)) + (g & 1) * 4) = v1;
+        const int y = tile >> 1;
+        if (y == 0 || y == kSide - 1) {  // the halo copy of the row (uniform over the wave)
+            const int h = (y == 0 ? kSide : -kSide) * kActRow;
+            *reinterpret_cast<bf16x4 *>(out + h + act_off(p, g >> 1) + (g & 1) * 4) = v0;
+            *reinterpret_cast<bf16x4 *>(out + h + act_off(p, 2 + (g >> 1)) + (g & 1) * 4) = v1;
+        }
         if (gout) {
             *reinterpret_cast<bf16x4 *>(gout + p * kC + g * 4) = v0;
             *reinterpret_cast<bf16x4 *>(gout + p * kC + 16 + g * 4) = v1;
@@ -293,16 +308,18 @@ struct FwdArgs {
 };
 
 // One 3x3, 32 -> 32 layer on MFMA. in/out are [pixel][channel] BF16 in LDS
-// (chunks permuted, act_off). The product is D[co][pixel] = W[co][ci]
-// X[ci][pixel] per tap (A: weights, held in registers; B: 8 channels of one
-// pixel per lane, one 16-byte LDS read), so each lane ends with 4
-// consecutive output channels of one pixel and stores them with one 8-byte
-// write. Each wave takes two 16-pixel tiles at a time: four independent
-// accumulation chains per tap. With POOL the ReLU outputs are summed per
-// channel into pool_part[wave][32] instead of being stored. Not inlined:
-// inlined into k_forward, its ~200 live registers (weights of the nine
-// taps, prefetched operands) spilled to scratch; as a call the layer has the
-// register file to itself (measured 1.14 x faster).
+// (chunks permuted, act_off; halo rows). The product is D[co][pixel] =
+// W[co][ci] X[ci][pixel] per tap (A: weights, held in registers; B: 8
+// channels of one pixel per lane, one 16-byte LDS read), so each lane ends
+// with 4 consecutive output channels of one pixel and stores them with one
+// 8-byte write. Each wave takes its eight 16-pixel tiles one at a time: the
+// nine operand reads of a tile are issued together, then its 18 MFMAs (two
+// accumulation chains, one per 16-channel half). The layer is bound by
+// instruction issue more than by LDS latency: cheap addressing (below) gained
+// 1.25x, while deeper read pipelines gained little or nothing. With POOL the
+// ReLU outputs are summed per channel into pool_part[wave][32] instead of
+// being stored. Not inlined: inlined into k_forward, its live registers
+// spilled to scratch; as a call the layer has the register file to itself.
 // Address-space-qualified element types: a generic pointer makes the
 // compiler emit flat memory instructions, which count against the LDS wait
 // counter too, so every MFMA would wait for all LDS reads in flight.
@@ -316,7 +333,7 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
                                                     const float *__restrict__ bias,
                                                     __bf16 *__restrict__ gout_p, float *pool_part)
 {
-    constexpr int U = 2;  // tiles per iteration
+    constexpr int U = 1;  // tiles per iteration (2: more registers, callee-saved spills, slower)
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
     typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
@@ -354,28 +371,44 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
 #pragma unroll
         for (int i = 0; i < 4; ++i) bb[ct][i] = bg[ct * 16 + g * 4 + i];
     float ps[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    for (int tile = wave; tile < kPix / 16; tile += U * kWaves) {
-        int y[U];
+    // The wave's tiles are rows y0 + 4 k (k = 0..7, y0 = wave / 2) of one
+    // column half; with the halo rows, the read of tap (dy, dx) of row
+    // y0 + 4 k is at base[dx] + (4 k + dy) rows, a compile-time offset.
+    const int y0 = wave >> 1;
+    const lds_bf16 *base[3];
 #pragma unroll
-        for (int u = 0; u < U; ++u) y[u] = (tile + u * kWaves) >> 1;
+    for (int d = 0; d < 3; ++d) base[d] = in + y0 * kActRow + colp[d];
+    lds_bf16 *obase = out + y0 * kActRow;
+#pragma unroll 1
+    for (int it = 0; it < kPix / 16 / (U * kWaves); ++it) {
         f32x4 acc[U][2];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) acc[u][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 xb[9][U];
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xb[t][u] = *reinterpret_cast<const lds_bf16x8 *>(
+                    base[tap_dx(t) + 1] + (4 * (it * U + u) + tap_dy(t)) * kActRow);
+        // all reads of the iteration are issued before its first MFMA (left
+        // to itself the scheduler reuses one register and waits on each read)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int rowp = wrap32(y[u] + tap_dy(t)) * (kSide * kC);
-                const bf16x8 xb = *reinterpret_cast<const lds_bf16x8 *>(in + rowp + colp[tap_dx(t) + 1]);
-                acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][0], xb, acc[u][0], 0, 0, 0);
-                acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][1], xb, acc[u][1], 0, 0, 0);
+                acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][0], xb[t][u], acc[u][0], 0, 0, 0);
+                acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][1], xb[t][u], acc[u][1], 0, 0, 0);
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int p = y[u] * kSide + col0;  // D column = pixel
+            const int k = it * U + u;
+            const int y = y0 + 4 * k;
+            const int p = y * kSide + col0;  // D column = pixel
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
                 bf16x4 v;
@@ -385,7 +418,15 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
                     if (POOL) ps[ct][i] += r;
                     v[i] = (__bf16)r;
                 }
-                if (!POOL) *reinterpret_cast<lds_bf16x4 *>(out + y[u] * (kSide * kC) + op[ct]) = v;
+                if (!POOL) {
+                    *reinterpret_cast<lds_bf16x4 *>(obase + 4 * k * kActRow + op[ct]) = v;
+                    // rows 0 and 31 also go to their halo copies: k = 0 with
+                    // y0 = 0 and k = 7 with y0 = 3 (uniform over the wave)
+                    if (k == 0 && y0 == 0)
+                        *reinterpret_cast<lds_bf16x4 *>(obase + kSide * kActRow + op[ct]) = v;
+                    if (k == kSide / 4 - 1 && y0 == 3)
+                        *reinterpret_cast<lds_bf16x4 *>(obase + (4 * k - kSide) * kActRow + op[ct]) = v;
+                }
                 if (gout) *reinterpret_cast<glb_bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
             }
         }
@@ -408,10 +449,10 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
 __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __bf16 *bufA = reinterpret_cast<__bf16 *>(smem);
-    __bf16 *bufB = bufA + kPix * kC;
-    float *xs = reinterpret_cast<float *>(bufB + kPix * kC);  // [1024]
-    float *pool_part = xs + kPix;                             // [8][32]
+    __bf16 *bufA = reinterpret_cast<__bf16 *>(smem) + kActRow;  // row 0 of a buffer with halo rows
+    __bf16 *bufB = bufA + kActElems;
+    float *xs = reinterpret_cast<float *>(bufB - kActRow + kActElems) + kSide;  // [1024], halo rows around it
+    float *pool_part = xs + kPix + kSide;                     // [8][32]
     float *red = pool_part + kWaves * kC;                      // [8]
     float *head = red + kWaves;                                // [37]
     float *tmp = head + kZ + 3;                                // [128]
@@ -435,6 +476,8 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
             const float x0 = v0 - m, x1 = v1 - m;
             xs[tid] = x0;
             xs[tid + kT] = x1;
+            if (tid < kSide) xs[kPix + tid] = x0;                // row 32 = row 0
+            if (tid >= kT - kSide) xs[tid + kT - kPix] = x1;    // row -1 = row 31
             __syncthreads();
             if (a.stats && t == 0) {
                 // variance and lag-1 correlations of the centred field (periodic)
@@ -876,7 +919,7 @@ SurLayout sur_layout(int batch, bool train)
     return L;
 }
 
-constexpr size_t kFwdLds = 2 * kPix * kC * 2 + (kPix + kWaves * kC + kWaves + kZ + 3 + 128 + 3 * kWaves) * 4;
+constexpr size_t kFwdLds = 2 * kActElems * 2 + (kPix + 2 * kSide + kWaves * kC + kWaves + kZ + 3 + 128 + 3 * kWaves) * 4;
 constexpr size_t kBwdLds = 2 * kPix * kC * 2 + (kPix + kWaves + kC) * 4;
 
 lbm_status check_ws(void *d_ws, size_t ws_bytes, size_t need, const char *fn)
