@@ -229,12 +229,15 @@ def lbm_init(p: lbm_params, d_perm, d_force, d_ws, ws_bytes: int, stream=None) -
     return h
 
 
-def lbm_step(h, max_steps: int, tol: float = 0.0, check_every: int = 0):
+def lbm_step(h, max_steps: int, tol: float = 0.0, check_every: int = 0, mean: bool = True):
     """Returns (status, steps_done, mean_u); raises on errors other than
-    LBM_ENOTCONV and LBM_ENONFINITE, which are returned."""
+    LBM_ENOTCONV and LBM_ENONFINITE, which are returned. With mean=False no
+    mean velocity is asked for (mean_u NULL): the call then waits for the
+    device only at the checks that fall within it, and mean_u is NaN."""
     steps = ctypes.c_int64(0)
-    mu = (ctypes.c_double * 2)()
-    st = lib().lbm_step(h, int(max_steps), float(tol), int(check_every), ctypes.byref(steps), mu)
+    mu = (ctypes.c_double * 2)(np.nan, np.nan)
+    st = lib().lbm_step(h, int(max_steps), float(tol), int(check_every), ctypes.byref(steps),
+                        mu if mean else None)
     if st not in (LBM_OK, LBM_ENOTCONV, LBM_ENONFINITE):
         _raise(st, "lbm_step")
     return st, steps.value, np.array([mu[0], mu[1]])
@@ -460,8 +463,8 @@ class FineSolver:
         self.ws = _workspace(nbytes, self.device)
         self.h = lbm_init(p, self.kappa, self.force, self.ws, nbytes)
 
-    def step(self, max_steps, tol=0.0, check_every=0):
-        return lbm_step(self.h, max_steps, tol, check_every)
+    def step(self, max_steps, tol=0.0, check_every=0, mean=True):
+        return lbm_step(self.h, max_steps, tol, check_every, mean)
 
     def fields(self):
         import torch
