@@ -302,9 +302,12 @@ __device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, i
         gy = k.hegy * rho;
     }
     const A hx = jx + gx, hy = jy + gy;
-    A mx, my;  // rho u_eq = 2 tau M h + (1 - 2 tau) j with M = I - E
+    const A om = k.om, omc = k.omc;
+    A s0, b, bx, by, cc, cx, cy;
     if constexpr (sizeof(A) == 8) {
-        // FP64: M = I - E formed exactly enough, then the product
+        // rho u_eq = 2 tau M h + (1 - 2 tau) j with M = I - E, formed exactly
+        // enough in FP64, then the weights
+        A mx, my;
         if (PK == 1) {
             const A tD = k.twotau - k.twotau * (A)cm.ld(0, c);
             mx = tD * hx + k.omtt * jx;
@@ -315,28 +318,45 @@ __device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, i
             mx = k.twotau * ((hx - e00 * hx) - e01 * hy) + k.omtt * jx;
             my = k.twotau * ((hy - e11 * hy) - e10 * hx) + k.omtt * jy;
         }
+        s0 = (A)(4.0 / 9.0) * om * dr;
+        b = (A)(1.0 / 9.0) * om * dr;
+        bx = (A)(1.0 / 3.0) * om * mx;
+        by = (A)(1.0 / 3.0) * om * my;
+        cc = (A)(1.0 / 36.0) * om * dr;
+        cx = (A)(1.0 / 12.0) * om * mx;
+        cy = (A)(1.0 / 12.0) * om * my;
     } else {
-        // FP32: = j + 2 tau eps rho G / 2 - 2 tau E h, so the drag enters as
-        // the small correction 2 tau E h and keeps its relative precision
+        // FP32: every rounded constant that multiplies a conserved or slowly
+        // relaxing quantity would bias it by a fixed fraction each step, which
+        // the slow modes of the flow accumulate (measured 6.5e-5 of the
+        // velocity after 20 000 steps at tau 0.8). So:
+        //  * om rho u_eq = om j + 2 (eps rho G / 2 - E h): (1/tau) (2 tau) is
+        //    the exact 2, not a product of two rounded constants;
+        //  * the rest weight and the diagonal momentum weight are remainders,
+        //    so the nine terms sum to om dr and om rho u_eq up to unbiased
+        //    rounding (the subtraction in cx is exact by Sterbenz's lemma);
+        //  * omc = 1 - om exactly (set on the host).
+        A ex, ey;  // E h
         if (PK == 1) {
-            const A tE = k.twotau * (A)cm.ld(0, c);
-            mx = (jx + k.twotau * gx) - tE * hx;
-            my = (jy + k.twotau * gy) - tE * hy;
+            const A e = (A)cm.ld(0, c);
+            ex = e * hx;
+            ey = e * hy;
         } else {
             const A e00 = cm.ld(0, c), e01 = cm.ld(1, c);
             const A e10 = cm.ld(2, c), e11 = cm.ld(3, c);
-            mx = (jx + k.twotau * gx) - k.twotau * (e00 * hx + e01 * hy);
-            my = (jy + k.twotau * gy) - k.twotau * (e10 * hx + e11 * hy);
+            ex = e00 * hx + e01 * hy;
+            ey = e10 * hx + e11 * hy;
         }
+        const A Mx = om * jx + (A)2 * (gx - ex), My = om * jy + (A)2 * (gy - ey);
+        const A D = om * dr;
+        b = D * (A)(1.0 / 9.0);
+        cc = D * (A)(1.0 / 36.0);
+        s0 = D - (A)4 * (b + cc);
+        bx = Mx * (A)(1.0 / 3.0);
+        by = My * (A)(1.0 / 3.0);
+        cx = (Mx - (A)2 * bx) * (A)0.25;
+        cy = (My - (A)2 * by) * (A)0.25;
     }
-    const A om = k.om, omc = k.omc;
-    const A s0 = (A)(4.0 / 9.0) * om * dr;
-    const A b = (A)(1.0 / 9.0) * om * dr;
-    const A bx = (A)(1.0 / 3.0) * om * mx;
-    const A by = (A)(1.0 / 3.0) * om * my;
-    const A cc = (A)(1.0 / 36.0) * om * dr;
-    const A cx = (A)(1.0 / 12.0) * om * mx;
-    const A cy = (A)(1.0 / 12.0) * om * my;
     const A pp = cx + cy, qq = cx - cy;
     f[0] = omc * f[0] + s0;
     f[1] = omc * f[1] + (b + bx);
@@ -884,7 +904,10 @@ StepArgs<R> step_args(const lbm_handle *h)
     a.cstride = (int)L.cstride;
     const double tau = h->p.tau;
     a.om = (R)(1.0 / tau);
-    a.omc = (R)(1.0 - 1.0 / tau);
+    // 1 - om formed in the storage type: for tau in [1/2, 2] the subtraction
+    // is exact (Sterbenz), so om + omc = 1 and the FP32-arithmetic collision
+    // conserves mass without a bias from the rounded 1/tau
+    a.omc = (R)1 - a.om;
     a.twotau = (R)(2.0 * tau);
     a.omtt = (R)(1.0 - 2.0 * tau);
     a.hegx = (R)(0.5 * h->p.eps * h->p.gx);
