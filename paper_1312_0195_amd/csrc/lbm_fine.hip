@@ -303,7 +303,6 @@ __device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, i
     }
     const A hx = jx + gx, hy = jy + gy;
     const A om = k.om, omc = k.omc;
-    A s0, b, bx, by, cc, cx, cy;
     if constexpr (sizeof(A) == 8) {
         // rho u_eq = 2 tau M h + (1 - 2 tau) j with M = I - E, formed exactly
         // enough in FP64, then the weights
@@ -318,13 +317,24 @@ __device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, i
             mx = k.twotau * ((hx - e00 * hx) - e01 * hy) + k.omtt * jx;
             my = k.twotau * ((hy - e11 * hy) - e10 * hx) + k.omtt * jy;
         }
-        s0 = (A)(4.0 / 9.0) * om * dr;
-        b = (A)(1.0 / 9.0) * om * dr;
-        bx = (A)(1.0 / 3.0) * om * mx;
-        by = (A)(1.0 / 3.0) * om * my;
-        cc = (A)(1.0 / 36.0) * om * dr;
-        cx = (A)(1.0 / 12.0) * om * mx;
-        cy = (A)(1.0 / 12.0) * om * my;
+        // equilibrium terms: w_a om dr and 3 w_a e_a . om rho u_eq
+        const A s0 = (A)(4.0 / 9.0) * om * dr;
+        const A b = (A)(1.0 / 9.0) * om * dr;
+        const A bx = (A)(1.0 / 3.0) * om * mx;
+        const A by = (A)(1.0 / 3.0) * om * my;
+        const A cc = (A)(1.0 / 36.0) * om * dr;
+        const A cx = (A)(1.0 / 12.0) * om * mx;
+        const A cy = (A)(1.0 / 12.0) * om * my;
+        const A pp = cx + cy, qq = cx - cy;
+        f[0] = omc * f[0] + s0;
+        f[1] = omc * f[1] + (b + bx);
+        f[2] = omc * f[2] + (b + by);
+        f[3] = omc * f[3] + (b - bx);
+        f[4] = omc * f[4] + (b - by);
+        f[5] = omc * f[5] + (cc + pp);
+        f[6] = omc * f[6] + (cc - qq);
+        f[7] = omc * f[7] + (cc - pp);
+        f[8] = omc * f[8] + (cc + qq);
     } else {
         // FP32: every rounded constant that multiplies a conserved or slowly
         // relaxing quantity would bias it by a fixed fraction each step, which
@@ -335,38 +345,43 @@ __device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, i
         //  * the rest weight and the diagonal momentum weight are remainders,
         //    so the nine terms sum to om dr and om rho u_eq up to unbiased
         //    rounding (the subtraction in cx is exact by Sterbenz's lemma);
-        //  * omc = 1 - om exactly (set on the host).
-        A ex, ey;  // E h
+        //  * omc = 1 - om exactly (set on the host);
+        //  * every fused multiply-add written out and no other contraction,
+        //    so all kernels that inline this (interior and edge paths, one and
+        //    several steps per launch) round alike.
+#pragma clang fp contract(off)
+        A tx, ty;  // eps rho G / 2 - E h
         if (PK == 1) {
             const A e = (A)cm.ld(0, c);
-            ex = e * hx;
-            ey = e * hy;
+            tx = __builtin_fmaf(-e, hx, gx);
+            ty = __builtin_fmaf(-e, hy, gy);
         } else {
             const A e00 = cm.ld(0, c), e01 = cm.ld(1, c);
             const A e10 = cm.ld(2, c), e11 = cm.ld(3, c);
-            ex = e00 * hx + e01 * hy;
-            ey = e10 * hx + e11 * hy;
+            tx = gx - __builtin_fmaf(e00, hx, e01 * hy);
+            ty = gy - __builtin_fmaf(e10, hx, e11 * hy);
         }
-        const A Mx = om * jx + (A)2 * (gx - ex), My = om * jy + (A)2 * (gy - ey);
+        const A Mx = __builtin_fmaf(om, jx, (A)2 * tx), My = __builtin_fmaf(om, jy, (A)2 * ty);
         const A D = om * dr;
-        b = D * (A)(1.0 / 9.0);
-        cc = D * (A)(1.0 / 36.0);
-        s0 = D - (A)4 * (b + cc);
-        bx = Mx * (A)(1.0 / 3.0);
-        by = My * (A)(1.0 / 3.0);
-        cx = (Mx - (A)2 * bx) * (A)0.25;
-        cy = (My - (A)2 * by) * (A)0.25;
+        const A b = D * (A)(1.0 / 9.0);
+        const A cc = D * (A)(1.0 / 36.0);
+        const A s0 = __builtin_fmaf((A)-4, b + cc, D);
+        // momentum: 2 t3 M on the axes and 4 c12 M on the diagonals, with t3
+        // = fl(1/3) and c12 = (1 - 2 t3) / 4 exact in FP32: they sum to M
+        // exactly, each term rounded once
+        constexpr A t3 = (A)1 / (A)3, c12 = ((A)1 - (A)2 * t3) * (A)0.25;
+        const A cx = Mx * c12, cy = My * c12;
+        const A pp = cx + cy, qq = cx - cy;
+        f[0] = __builtin_fmaf(omc, f[0], s0);
+        f[1] = __builtin_fmaf(omc, f[1], __builtin_fmaf(Mx, t3, b));
+        f[2] = __builtin_fmaf(omc, f[2], __builtin_fmaf(My, t3, b));
+        f[3] = __builtin_fmaf(omc, f[3], __builtin_fmaf(-Mx, t3, b));
+        f[4] = __builtin_fmaf(omc, f[4], __builtin_fmaf(-My, t3, b));
+        f[5] = __builtin_fmaf(omc, f[5], cc + pp);
+        f[6] = __builtin_fmaf(omc, f[6], cc - qq);
+        f[7] = __builtin_fmaf(omc, f[7], cc - pp);
+        f[8] = __builtin_fmaf(omc, f[8], cc + qq);
     }
-    const A pp = cx + cy, qq = cx - cy;
-    f[0] = omc * f[0] + s0;
-    f[1] = omc * f[1] + (b + bx);
-    f[2] = omc * f[2] + (b + by);
-    f[3] = omc * f[3] + (b - bx);
-    f[4] = omc * f[4] + (b - by);
-    f[5] = omc * f[5] + (cc + pp);
-    f[6] = omc * f[6] + (cc - qq);
-    f[7] = omc * f[7] + (cc - pp);
-    f[8] = omc * f[8] + (cc + qq);
     }
 }
 

@@ -145,39 +145,77 @@ __device__ inline Consts<double>::Consts(const LocalArgs &a)
 // flow, so the stall moves down by the ratio of the two.
 //
 // The drag enters through its deficit E = 1 - D = h / (kappa + h),
-// h = eps nu / 2, as tE = 2 tau E; with j' = sum e f', rho = rho0 + sum f':
+// h = eps nu / 2; with j' = sum e f', rho = rho0 + sum f':
 //   rho u_eq - U = 2 tau D (U + j' + rho eps G / 2) + (1 - 2 tau)(U + j') - U
-//               = j' + 2 tau rho eps G / 2 - tE (U + j' + rho eps G / 2),
+//               = j' + 2 tau (rho eps G / 2 - E (U + j' + rho eps G / 2)),
 // every term of which is as small as the non-uniform flow or the drag.
-// tgx, tgy: 2 tau eps G / 2 of the item's drive; Ux, Uy: the reference U.
+// FP64 items take cE = 2 tau E per cell and tgx, tgy = 2 tau eps G / 2 of
+// the item's drive; FP32 items take cE = 2 E, tgx, tgy = 2 eps G / 2 and
+// form om (rho u_eq - U) as om j' + 2 (rho eps G / 2 - E (...)), with the
+// exact factor 2 = om 2 tau,
+// and weights that sum exactly (the rest weight and the diagonal momentum
+// weight as remainders): with rounded FP32 weights, and with (1/tau) (2 tau)
+// as a product of two rounded constants, every step would add a fixed
+// fraction (~3e-8) of the mass and momentum terms, a bias the slow relaxation
+// of a permeable patch accumulates. Ux, Uy: the reference U.
 template <typename P>
-__device__ __forceinline__ void collide(P f[9], P tE, P hegx, P hegy, P tgx, P tgy, P Ux, P Uy,
+__device__ __forceinline__ void collide(P f[9], P cE, P hegx, P hegy, P tgx, P tgy, P Ux, P Uy,
                                         const Consts<P> &k)
 {
     const P dr = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const P jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
     const P jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
     const P rho = P(1) + dr;
-    const P mx = (jx + tgx * rho) - tE * (jx + (hegx * rho + Ux));
-    const P my = (jy + tgy * rho) - tE * (jy + (hegy * rho + Uy));
     const P om = k.om, omc = k.omc;
-    const P s0 = (P(4) / P(9)) * om * dr;
-    const P b = (P(1) / P(9)) * om * dr;
-    const P bx = (P(1) / P(3)) * om * mx;
-    const P by = (P(1) / P(3)) * om * my;
-    const P cc = (P(1) / P(36)) * om * dr;
-    const P cx = (P(1) / P(12)) * om * mx;
-    const P cy = (P(1) / P(12)) * om * my;
-    const P pp = cx + cy, qq = cx - cy;
-    f[0] = omc * f[0] + s0;
-    f[1] = omc * f[1] + (b + bx);
-    f[2] = omc * f[2] + (b + by);
-    f[3] = omc * f[3] + (b - bx);
-    f[4] = omc * f[4] + (b - by);
-    f[5] = omc * f[5] + (cc + pp);
-    f[6] = omc * f[6] + (cc - qq);
-    f[7] = omc * f[7] + (cc - pp);
-    f[8] = omc * f[8] + (cc + qq);
+    if constexpr (sizeof(P) == 8) {
+        const P mx = (jx + tgx * rho) - cE * (jx + (hegx * rho + Ux));
+        const P my = (jy + tgy * rho) - cE * (jy + (hegy * rho + Uy));
+        const P s0 = (P(4) / P(9)) * om * dr;
+        const P b = (P(1) / P(9)) * om * dr;
+        const P bx = (P(1) / P(3)) * om * mx;
+        const P by = (P(1) / P(3)) * om * my;
+        const P cc = (P(1) / P(36)) * om * dr;
+        const P cx = (P(1) / P(12)) * om * mx;
+        const P cy = (P(1) / P(12)) * om * my;
+        const P pp = cx + cy, qq = cx - cy;
+        f[0] = omc * f[0] + s0;
+        f[1] = omc * f[1] + (b + bx);
+        f[2] = omc * f[2] + (b + by);
+        f[3] = omc * f[3] + (b - bx);
+        f[4] = omc * f[4] + (b - by);
+        f[5] = omc * f[5] + (cc + pp);
+        f[6] = omc * f[6] + (cc - qq);
+        f[7] = omc * f[7] + (cc - pp);
+        f[8] = omc * f[8] + (cc + qq);
+    } else {
+        // every fused multiply-add written out and no other contraction, so
+        // the launches compiled for 1, 2 or 4 cells per thread round alike
+#pragma clang fp contract(off)
+        // cE = 2 E, tgx = 2 eps G / 2 here (doublings are exact), so
+        // t = 2 (rho eps G / 2 - E (j' + rho eps G / 2 + U)) in one rounding
+        const P tx = __builtin_fmaf(-cE, jx + __builtin_fmaf(hegx, rho, Ux), tgx * rho);
+        const P ty = __builtin_fmaf(-cE, jy + __builtin_fmaf(hegy, rho, Uy), tgy * rho);
+        const P Mx = __builtin_fmaf(om, jx, tx), My = __builtin_fmaf(om, jy, ty);
+        const P D = om * dr;
+        const P b = D * (P(1) / P(9));
+        const P cc = D * (P(1) / P(36));
+        const P s0 = __builtin_fmaf(P(-4), b + cc, D);
+        // momentum: 2 t3 M on the axes and 4 c12 M on the diagonals, with t3
+        // = fl(1/3) and c12 = (1 - 2 t3) / 4 exact in FP32: they sum to M
+        // exactly, each term rounded once
+        constexpr P t3 = P(1) / P(3), c12 = (P(1) - P(2) * t3) * P(0.25);
+        const P cx = Mx * c12, cy = My * c12;
+        const P pp = cx + cy, qq = cx - cy;
+        f[0] = __builtin_fmaf(omc, f[0], s0);
+        f[1] = __builtin_fmaf(omc, f[1], __builtin_fmaf(Mx, t3, b));
+        f[2] = __builtin_fmaf(omc, f[2], __builtin_fmaf(My, t3, b));
+        f[3] = __builtin_fmaf(omc, f[3], __builtin_fmaf(-Mx, t3, b));
+        f[4] = __builtin_fmaf(omc, f[4], __builtin_fmaf(-My, t3, b));
+        f[5] = __builtin_fmaf(omc, f[5], cc + pp);
+        f[6] = __builtin_fmaf(omc, f[6], cc - qq);
+        f[7] = __builtin_fmaf(omc, f[7], cc - pp);
+        f[8] = __builtin_fmaf(omc, f[8], cc + qq);
+    }
 }
 
 // CPT: the most cells any thread of this launch owns (1, 2 or 4); the
@@ -207,7 +245,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
     P Ux = 0, Uy = 0;  // reference momentum of the rebased state
     double hegx_d = 0.0, hegy_d = 0.0;
     // per-cell registers
-    P f0[CPT], tE[CPT];  // rest population and 2 tau (1 - D) of each owned cell
+    P f0[CPT], tE[CPT];  // rest population and scaled drag deficit of each owned cell (cE of collide)
     int xy[CPT];
 
     bool need_item = true;
@@ -240,8 +278,8 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                 hegy = drive == 1 ? kc.heg : P(0);
                 hegx_d = drive == 0 ? a.heg_d : 0.0;
                 hegy_d = drive == 1 ? a.heg_d : 0.0;
-                tgx = (P)(a.twotau_d * hegx_d);
-                tgy = (P)(a.twotau_d * hegy_d);
+                tgx = (P)((sizeof(P) == 8 ? a.twotau_d : 2.0) * hegx_d);
+                tgy = (P)((sizeof(P) == 8 ? a.twotau_d : 2.0) * hegy_d);
                 Ux = Uy = P(0);
                 steps = 0;
                 have_prev = false;
@@ -255,7 +293,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                         const int fx = (x0 + x) % a.fnx, fy = (y0 + y) % a.fny;
                         const double kap = a.field[(size_t)fy * a.fnx + fx];
                         // kappa <= 0 or NaN poisons the item: it ends flagged non-finite
-                        tE[k] = (kap > 0.0) ? (P)(a.twotau_d * a.h / (kap + a.h))
+                        tE[k] = (kap > 0.0) ? (P)((sizeof(P) == 8 ? a.twotau_d : 2.0) * a.h / (kap + a.h))
                                             : (P)__longlong_as_double(0x7ff8000000000000LL);
                         f0[k] = P(0);
 #pragma unroll
@@ -353,7 +391,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                     qy += jpy;
                     const double jx = (double)Ux + jpx, jy = (double)Uy + jpy;
                     const double rho = 1.0 + dr;
-                    const double D = 1.0 - (double)tE[k] / a.twotau_d;
+                    const double D = 1.0 - (double)tE[k] / (sizeof(P) == 8 ? a.twotau_d : 2.0);
                     // oversampling: only the inner window enters the average
                     const int x = xy[k] & 255, y = xy[k] >> 8;
                     const int m = a.margin;
@@ -804,7 +842,7 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     a.steps_out = d_steps;
     a.flags_out = d_flags;
     a.om = (float)(1.0 / lp->tau);
-    a.omc = (float)(1.0 - 1.0 / lp->tau);
+    a.omc = 1.0f - a.om;  // exact for tau in [1/2, 2]: om + omc = 1 in FP32
     a.twotau = (float)(2.0 * lp->tau);
     a.omtt = (float)(1.0 - 2.0 * lp->tau);
     a.heg = (float)(0.5 * lp->eps * lp->g);

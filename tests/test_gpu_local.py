@@ -90,6 +90,12 @@ def test_local_other_tau(L, tau):
 
 @pytest.mark.parametrize("block_threads", [256, 512, 1024])
 def test_local_tile_choices_agree(L, block_threads):
+    """Every tile layout gives the same K_eff to the solver's tolerance: the
+    per-cell arithmetic is the same, but the FP64 sums of the convergence
+    check depend on how the cells are spread over waves, so an item can stop
+    one check (100 steps) earlier or later in another layout (measured: 3e-8
+    of the tensor; 1e-6 of each diagonal entry and of the larger diagonal for
+    the off-diagonal ones is required)."""
     field = I.lognormal_kappa(128, 128, 1.5, 8.0, seed=3)
     x0, y0, s = I.tile_patches(128, 128, 32)
     ref = L.local_keff(field, x0, y0, s, TAU, EPS, NU, G, tol=GPU_TOL)
@@ -101,7 +107,9 @@ def test_local_tile_choices_agree(L, block_threads):
         r = L.local_keff(field, x0, y0, s, TAU, EPS, NU, G, tol=GPU_TOL, tiles=tiles,
                          block_threads=block_threads)
         assert (r.flags == 0).all()
-        assert np.allclose(r.keff, ref.keff, rtol=1e-6, atol=1e-9)
+        scale = np.maximum(np.abs(ref.keff[:, 0]), np.abs(ref.keff[:, 3]))
+        assert np.all(np.abs(r.keff[:, [0, 3]] / ref.keff[:, [0, 3]] - 1) < 1e-6)
+        assert np.all(np.abs(r.keff[:, [1, 2]] - ref.keff[:, [1, 2]]) / scale[:, None] < 1e-6)
 
 
 def test_local_schedule_changes_only_the_order(L):
