@@ -446,6 +446,17 @@ static_assert(kDeep > 4, "the deepest kernel must take more than 4 steps");
 template <> struct TileD<double, 2> : TileShape<32, 16, 256> {};
 template <> struct TileD<double, 4> : TileShape<LBM_TILE4D> {};
 template <> struct TileD<double, LBM_DEEP> : TileShape<LBM_TILE6D> {};
+// Per arithmetic type A: FP32 collision arithmetic needs 61 VGPRs where FP64
+// needs 96, so two 768-thread workgroups (24 waves) fit a CU beside each
+// other's 80 KB of LDS. Measured per six-step launch on 2048^2 (us): 50 x 24
+// on 768 threads 89.8, 48 x 24 90.8, 56 x 20 90.7; 48 x 24 on 512 99.3, on
+// 704 103.0, on 640, 832, 896 or 1024 threads 138-153; five steps per launch
+// with 56 x 24 on 768 97.6.
+#ifndef LBM_TILE6F
+#define LBM_TILE6F 50, 24, 768
+#endif
+template <typename R, int D, typename A> struct TileDA : TileD<R, D> {};
+template <> struct TileDA<float, LBM_DEEP, float> : TileShape<LBM_TILE6F> {};
 
 // D time steps per launch (temporal blocking). Phase 1 takes step t on the
 // workgroup's tile plus a (D - 1)-cell halo, pulling from HBM and keeping the
@@ -457,9 +468,9 @@ template <> struct TileD<double, LBM_DEEP> : TileShape<LBM_TILE6D> {};
 // steps (plus the halo, which neighbouring tiles mostly find in L2). Loads and
 // stores go through BMem (32-bit offsets, plane bases in scalar registers).
 template <typename R, bool WALLS, int PK, bool FF, int D, typename A = double>
-__global__ __launch_bounds__((TileD<R, D>::BS)) void k_stepd(StepArgs<R> a)
+__global__ __launch_bounds__((TileDA<R, D, A>::BS)) void k_stepd(StepArgs<R> a)
 {
-    constexpr int TX = TileD<R, D>::TX, TY = TileD<R, D>::TY, BS = TileD<R, D>::BS;
+    constexpr int TX = TileDA<R, D, A>::TX, TY = TileDA<R, D, A>::TY, BS = TileDA<R, D, A>::BS;
     constexpr int H = D - 1;
     constexpr int AX = TX + 2 * H, AY = TY + 2 * H, AN = AX * AY;
     constexpr int KM = (D > 2) ? ((AX - 2) * (AY - 2) + BS - 1) / BS : 1;  // cells per thread, phase 2
@@ -998,7 +1009,9 @@ struct StepDFn {
         const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
         if constexpr (std::is_same<R, float>::value && PK != 0) {
             if (h->p.pop_dtype == LBM_F32_FAST) {
-                hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D, float>), dim3(ntx * nty), dim3(BS), 0, h->stream,
+                using TF = TileDA<R, D, float>;
+                const int fx = (h->p.nx + TF::TX - 1) / TF::TX, fy = (h->p.ny + TF::TY - 1) / TF::TY;
+                hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D, float>), dim3(fx * fy), dim3(TF::BS), 0, h->stream,
                                    step_args<R>(h));
                 return;
             }
