@@ -25,10 +25,12 @@
 //
 // Forward: one workgroup (8 waves) per patch at a time, persistent over the
 // batch. Activations stay in LDS ([pixel][channel] BF16 with the channel
-// chunks of each pixel permuted (act_off), 64 KB per layer,
-// two buffers); a 16x16x32 MFMA takes 16 pixels x 32 input channels of one
-// tap, so a 3x3 layer is 9 MFMAs per 16-pixel x 16-channel output tile. The
-// last conv layer is pooled straight from the accumulators.
+// chunks of each pixel permuted (act_off), 64 KB per layer plus halo rows,
+// two buffers), and the BF16 weights of the 32 -> 32 layers pass through an
+// 18 KB LDS buffer, one layer ahead; a 16x16x32 MFMA takes 16 pixels x 32
+// input channels of one tap, so a 3x3 layer is 9 MFMAs per 16-pixel x
+// 16-channel output tile. The last conv layer is pooled straight from the
+// accumulators.
 //
 // Training: the forward also stores a1..a4 (BF16) and the pooled features;
 // the head backward runs per patch in FP32; the conv backward walks layers
@@ -246,32 +248,39 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
         const int tt = t < 9 ? t : 4;
         off[j] = tap_dy(tt) * kSide + wrap32(x0 + n + tap_dx(tt));  // rows -1 and 32 are xs's halo
     }
-    for (int tile = wave; tile < kPix / 16; tile += kWaves) {
-        const int ybase = (tile >> 1) * kSide;
-        bf16x8 a;
+    // two tiles per iteration, all sixteen reads issued before either MFMA
+    for (int tile = wave; tile < kPix / 16; tile += 2 * kWaves) {
+        bf16x8 a[2];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = (__bf16)xs[ybase + off[j]];
-        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-        const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, a, z, 0, 0, 0);
-        const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, a, z, 0, 0, 0);
-        const int p = ybase + x0 + n;  // D column = pixel
-        bf16x4 v0, v1;
+        for (int u = 0; u < 2; ++u) {
+            const int ybase = ((tile + u * kWaves) >> 1) * kSide;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            v0[i] = (__bf16)fmaxf(acc0[i] + b0[i], 0.0f);
-            v1[i] = (__bf16)fmaxf(acc1[i] + b1[i], 0.0f);
+            for (int j = 0; j < 8; ++j) a[u][j] = (__bf16)xs[ybase + off[j]];
         }
-        *reinterpret_cast<bf16x4 *>(out + act_off(p, g >> 1) + (g & 1) * 4) = v0;
-        *reinterpret_cast<bf16x4 *>(out + act_off(p, 2 + (g >> 1)) + (g & 1) * 4) = v1;
-        const int y = tile >> 1;
-        if (y == 0 || y == kSide - 1) {  // the halo copy of the row (uniform over the wave)
-            const int h = (y == 0 ? kSide : -kSide) * kActRow;
-            *reinterpret_cast<bf16x4 *>(out + h + act_off(p, g >> 1) + (g & 1) * 4) = v0;
-            *reinterpret_cast<bf16x4 *>(out + h + act_off(p, 2 + (g >> 1)) + (g & 1) * 4) = v1;
-        }
-        if (gout) {
-            *reinterpret_cast<bf16x4 *>(gout + p * kC + g * 4) = v0;
-            *reinterpret_cast<bf16x4 *>(gout + p * kC + 16 + g * 4) = v1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+            const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, a[u], z, 0, 0, 0);
+            const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, a[u], z, 0, 0, 0);
+            const int y = (tile + u * kWaves) >> 1;
+            const int p = y * kSide + x0 + n;  // D column = pixel
+            bf16x4 v0, v1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v0[i] = (__bf16)fmaxf(acc0[i] + b0[i], 0.0f);
+                v1[i] = (__bf16)fmaxf(acc1[i] + b1[i], 0.0f);
+            }
+            *reinterpret_cast<bf16x4 *>(out + act_off(p, g >> 1) + (g & 1) * 4) = v0;
+            *reinterpret_cast<bf16x4 *>(out + act_off(p, 2 + (g >> 1)) + (g & 1) * 4) = v1;
+            if (y == 0 || y == kSide - 1) {  // the halo copy of the row (uniform over the wave)
+                const int h = (y == 0 ? kSide : -kSide) * kActRow;
+                *reinterpret_cast<bf16x4 *>(out + h + act_off(p, g >> 1) + (g & 1) * 4) = v0;
+                *reinterpret_cast<bf16x4 *>(out + h + act_off(p, 2 + (g >> 1)) + (g & 1) * 4) = v1;
+            }
+            if (gout) {
+                *reinterpret_cast<bf16x4 *>(gout + p * kC + g * 4) = v0;
+                *reinterpret_cast<bf16x4 *>(gout + p * kC + 16 + g * 4) = v1;
+            }
         }
     }
 }
@@ -327,9 +336,17 @@ typedef __attribute__((address_space(3))) __bf16 lds_bf16;     // LDS (32-bit ad
 typedef __attribute__((address_space(1))) __bf16 glb_bf16;     // global memory
 typedef __attribute__((address_space(1))) const float glb_f32;
 
+// The packed BF16 weights of one 32 -> 32 layer (9 x 32 x 32) as 1152
+// 16-byte chunks (row = tap * 32 + output channel, 4 chunks of 8 input
+// channels per row); in LDS at act_off(row, chunk), the permutation of the
+// activation buffers, so the 16 rows a wave reads per operand spread over
+// the banks.
+constexpr int kWChunks = 9 * kC * kC / 8;
+
 template <bool POOL>
 __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ in_p, __bf16 *__restrict__ out_p,
-                                                    const __bf16 *__restrict__ wfl,
+                                                    __bf16 *__restrict__ wbuf_p,
+                                                    const __bf16 *__restrict__ next_w,
                                                     const float *__restrict__ bias,
                                                     __bf16 *__restrict__ gout_p, float *pool_part)
 {
@@ -342,7 +359,8 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
     const lds_bf16 *in = (const lds_bf16 *)in_p;
     lds_bf16 *out = (lds_bf16 *)out_p;
     glb_bf16 *gout = (glb_bf16 *)gout_p;
-    const glb_bf16 *wg = (const glb_bf16 *)wfl;
+    lds_bf16 *wbuf = (lds_bf16 *)wbuf_p;
+    const glb_bf16 *nw = (const glb_bf16 *)next_w;
     glb_f32 *bg = (glb_f32 *)bias;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -359,12 +377,32 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
     for (int d = 0; d < 3; ++d) colp[d] = act_off(wrap32(x0 + n + d - 1), g);
     const int col0 = x0 + n;
     const int op[2] = {act_off(col0, g >> 1) + (g & 1) * 4, act_off(col0, 2 + (g >> 1)) + (g & 1) * 4};
+    // This layer's weights come from LDS, where the previous layer (or the
+    // set-up before the first patch) staged them: every wave needs all of
+    // them in registers, and eight waves reading 18 KB each through the
+    // vector memory path cost about a third of the forward's time. The next
+    // layer's weights are read from global memory now and written to the
+    // same LDS buffer once every wave holds its copy of these.
     bf16x8 w[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
-            w[t][ct] = *reinterpret_cast<glb_bf16x8 *>(wg + (t * kC + ct * 16 + n) * kC + g * 8);
+            w[t][ct] = *reinterpret_cast<const lds_bf16x8 *>(wbuf + act_off(t * kC + ct * 16 + n, g));
+    constexpr int kPer = (kWChunks + kT - 1) / kT;
+    bf16x8 nx[kPer];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = tid + j * kT;
+        if (i < kWChunks) nx[j] = *reinterpret_cast<glb_bf16x8 *>(nw + (i >> 2) * kC + (i & 3) * 8);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = tid + j * kT;
+        if (i < kWChunks) *reinterpret_cast<lds_bf16x8 *>(wbuf + act_off(i >> 2, i & 3)) = nx[j];
+    }
     float bb[2][4];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct)
@@ -455,8 +493,9 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     float *pool_part = xs + kPix + kSide;                     // [8][32]
     float *red = pool_part + kWaves * kC;                      // [8]
     float *head = red + kWaves;                                // [37]
-    float *tmp = head + kZ + 3;                                // [128]
-    float *red3 = tmp + 128;                                   // [3][8]
+    float *tmp = head + kZ + 3;                                // [16]
+    float *red3 = tmp + 16;                                    // [3][8]
+    __bf16 *wbuf = reinterpret_cast<__bf16 *>(red3 + 3 * kWaves);  // staged conv weights [1152 x 8]
     const int tid = threadIdx.x;
     const float *prm = a.prm;
 
@@ -464,6 +503,12 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     // index, then takes the next free one), so workgroups that start late --
     // behind other work on the device -- simply take fewer patches.
     __shared__ int claimed;
+    // conv2's weights into LDS before the first patch; each conv layer then
+    // stages the next one's (conv4 stages conv2's for the next pass)
+    for (int i = tid; i < kWChunks; i += kT)
+        *reinterpret_cast<bf16x8 *>(wbuf + act_off(i >> 2, i & 3)) =
+            *reinterpret_cast<const bf16x8 *>(a.wf + (i >> 2) * kC + (i & 3) * 8);
+    __syncthreads();
     for (int b = blockIdx.x; b < a.batch;) {
         const float *lk = a.logk + (size_t)b * kPix;
         float acc0 = 0.0f, acc1 = 0.0f;  // averaged prediction (thread 0)
@@ -507,11 +552,11 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
             __bf16 *g2 = a.acts ? a.acts + ((size_t)1 * a.batch + b) * kPix * kC : nullptr;
             __bf16 *g3 = a.acts ? a.acts + ((size_t)2 * a.batch + b) * kPix * kC : nullptr;
             __bf16 *g4 = a.acts ? a.acts + ((size_t)3 * a.batch + b) * kPix * kC : nullptr;
-            conv_mfma<false>(bufA, bufB, a.wf, prm + oB2, g2, pool_part);
+            conv_mfma<false>(bufA, bufB, wbuf, a.wf + 9 * kC * kC, prm + oB2, g2, pool_part);
             __syncthreads();
-            conv_mfma<false>(bufB, bufA, a.wf + 9 * kC * kC, prm + oB3, g3, pool_part);
+            conv_mfma<false>(bufB, bufA, wbuf, a.wf + 2 * 9 * kC * kC, prm + oB3, g3, pool_part);
             __syncthreads();
-            conv_mfma<true>(bufA, nullptr, a.wf + 2 * 9 * kC * kC, prm + oB4, g4, pool_part);
+            conv_mfma<true>(bufA, nullptr, wbuf, a.wf, prm + oB4, g4, pool_part);  // stages conv2's for the next pass
             __syncthreads();
             // ---- pooling and head (FP32) ----
             if (tid < kC) {
@@ -919,7 +964,11 @@ SurLayout sur_layout(int batch, bool train)
     return L;
 }
 
-constexpr size_t kFwdLds = 2 * kActElems * 2 + (kPix + 2 * kSide + kWaves * kC + kWaves + kZ + 3 + 128 + 3 * kWaves) * 4;
+constexpr size_t kFwdLds = 2 * kActElems * 2 + (kPix + 2 * kSide + kWaves * kC + kWaves + kZ + 3 + 16 + 3 * kWaves) * 4 +
+                           kWChunks * 16;
+static_assert((2 * kActElems * 2 + (kPix + 2 * kSide + kWaves * kC + kWaves + kZ + 3 + 16 + 3 * kWaves) * 4) % 16 == 0,
+              "the staged weights need 16-byte alignment");
+static_assert(kFwdLds + 64 <= 160 * 1024, "forward LDS exceeds a CU's 160 KB");
 constexpr size_t kBwdLds = 2 * kPix * kC * 2 + (kPix + kWaves + kC) * 4;
 
 lbm_status check_ws(void *d_ws, size_t ws_bytes, size_t need, const char *fn)
