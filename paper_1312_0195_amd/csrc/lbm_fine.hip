@@ -461,6 +461,10 @@ template <> struct TileD<double, LBM_DEEP> : TileShape<LBM_TILE6D> {};
 template <typename R, int D, typename A> struct TileDA : TileD<R, D> {};
 template <> struct TileDA<float, LBM_DEEP, float> : TileShape<LBM_TILE6F> {};
 template <> struct TileDA<float, 4, float> : TileShape<LBM_TILE4F> {};
+#ifndef LBM_TILE2F
+#define LBM_TILE2F 96, 18, 768  // two-step launches (us, 2048^2): 66.0 against 74.3 for 64 x 64 on 1024
+#endif
+template <> struct TileDA<float, 2, float> : TileShape<LBM_TILE2F> {};
 
 // D time steps per launch (temporal blocking). Phase 1 takes step t on the
 // workgroup's tile plus a (D - 1)-cell halo, pulling from HBM and keeping the
