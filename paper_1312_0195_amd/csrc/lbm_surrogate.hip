@@ -215,26 +215,48 @@ __device__ __forceinline__ void block_sum3_fixed(float &a, float &b, float &c, f
 // 32 -> 32 layers the weights are the A operand (16 output channels x 32
 // taps) and the taps of 16 pixels the B operand, so each lane ends with four
 // consecutive channels of one pixel and stores them with one 8-byte write.
+// conv1's A operands (W1 with the taps as K, zero beyond tap 8) and its bias
+// as this lane needs them. Loaded once per launch: read at every patch, the
+// sixteen guarded loads each waited for their own round trip to L2.
+struct Conv1W {
+    bf16x8 w0, w1;
+    float b0[4], b1[4];
+};
+__device__ __forceinline__ Conv1W conv1_weights(const float *__restrict__ prm)
+{
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, g = lane >> 4;
+    float v0[8], v1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {  // unconditional reads (tap clamped), so all are in flight together
+        const int t = min(g * 8 + j, 8);
+        v0[j] = prm[oW1 + t * kC + n];
+        v1[j] = prm[oW1 + t * kC + 16 + n];
+    }
+    Conv1W c;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const bool tap = g * 8 + j < 9;
+        c.w0[j] = (__bf16)(tap ? v0[j] : 0.0f);
+        c.w1[j] = (__bf16)(tap ? v1[j] : 0.0f);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        c.b0[i] = prm[oB1 + g * 4 + i];
+        c.b1[i] = prm[oB1 + 16 + g * 4 + i];
+    }
+    return c;
+}
+
 __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 *__restrict__ out,
-                                           const float *__restrict__ prm, __bf16 *__restrict__ gout)
+                                           const Conv1W &cw, __bf16 *__restrict__ gout)
 {
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = lane & 15, g = lane >> 4;  // n: output channel row of A / pixel of B; g: k-group
-    bf16x8 w0, w1;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int t = g * 8 + j;
-        w0[j] = (__bf16)(t < 9 ? prm[oW1 + t * kC + n] : 0.0f);
-        w1[j] = (__bf16)(t < 9 ? prm[oW1 + t * kC + 16 + n] : 0.0f);
-    }
-    float b0[4], b1[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        b0[i] = prm[oB1 + g * 4 + i];
-        b1[i] = prm[oB1 + 16 + g * 4 + i];
-    }
+    const bf16x8 w0 = cw.w0, w1 = cw.w1;
+    const float *b0 = cw.b0, *b1 = cw.b1;
     // Every tile of this wave has the same column half (kWaves is even), so
     // the offset of tap j from the tile's row start, wrapped in x, is fixed
     // per lane; the row wrap is the wrap of the whole 1024-pixel plane.
@@ -343,12 +365,12 @@ typedef __attribute__((address_space(1))) const float glb_f32;
 // the banks.
 constexpr int kWChunks = 9 * kC * kC / 8;
 
-template <bool POOL>
-__device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ in_p, __bf16 *__restrict__ out_p,
-                                                    __bf16 *__restrict__ wbuf_p,
-                                                    const __bf16 *__restrict__ next_w,
-                                                    const float *__restrict__ bias,
-                                                    __bf16 *__restrict__ gout_p, float *pool_part)
+template <bool POOL, bool PF, bool GOUT>
+__device__ __forceinline__ void conv_body(const __bf16 *__restrict__ in_p, __bf16 *__restrict__ out_p,
+                                          __bf16 *__restrict__ wbuf_p, const __bf16 *__restrict__ next_w,
+                                          const float *__restrict__ bias, __bf16 *__restrict__ gout_p,
+                                          float *__restrict__ pool_part, const float *__restrict__ pf, int pf_sym,
+                                          float *__restrict__ xs_stage)
 {
     constexpr int U = 1;  // tiles per iteration (2: more registers, callee-saved spills, slower)
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -377,37 +399,57 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
     for (int d = 0; d < 3; ++d) colp[d] = act_off(wrap32(x0 + n + d - 1), g);
     const int col0 = x0 + n;
     const int op[2] = {act_off(col0, g >> 1) + (g & 1) * 4, act_off(col0, 2 + (g >> 1)) + (g & 1) * 4};
+    // The bias is read from global memory first and waited for only where
+    // it is used (a wait at each read cost one L2 round trip per layer).
+    float bb[2][4];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bb[ct][i] = bg[ct * 16 + g * 4 + i];
     // This layer's weights come from LDS, where the previous layer (or the
     // set-up before the first patch) staged them: every wave needs all of
     // them in registers, and eight waves reading 18 KB each through the
-    // vector memory path cost about a third of the forward's time. The next
-    // layer's weights are read from global memory now and written to the
-    // same LDS buffer once every wave holds its copy of these.
+    // vector memory path cost about a third of the forward's time.
     bf16x8 w[9][2];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
             w[t][ct] = *reinterpret_cast<const lds_bf16x8 *>(wbuf + act_off(t * kC + ct * 16 + n, g));
-    constexpr int kPer = (kWChunks + kT - 1) / kT;
-    bf16x8 nx[kPer];
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int i = tid + j * kT;
-        if (i < kWChunks) nx[j] = *reinterpret_cast<glb_bf16x8 *>(nw + (i >> 2) * kC + (i & 3) * 8);
-    }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int i = tid + j * kT;
-        if (i < kWChunks) *reinterpret_cast<lds_bf16x8 *>(wbuf + act_off(i >> 2, i & 3)) = nx[j];
+    // the bias has arrived meanwhile: with no register loads in flight, the
+    // tiles wait for none of the loads below
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // Once every wave holds its copy (the barrier), the next layer's weights
+    // go from global memory straight into the same LDS buffer while this
+    // layer's tiles run. A load to LDS writes lane l's bytes at the wave's
+    // base + l x size, so each wave fills its own 2304 bytes of the buffer
+    // with two 16-byte and one 4-byte load per lane, and each lane reads the
+    // piece of the chunk whose permuted position (act_off) it fills. With PF
+    // the next pass's input goes the same way into the input plane (free
+    // once conv1 has run). Waited for at the end of the layer.
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef __attribute__((address_space(1))) const void glb_void;
+    static_assert(kWChunks % kWaves == 0 && kWChunks / kWaves == 2 * 64 + 16, "three loads per wave");
+    {
+        typedef __attribute__((address_space(3))) char lds_char;
+        lds_char *wb = (lds_char *)wbuf + wave * (kWChunks / kWaves) * 16;
+        auto src = [&](int q, int dw) {  // dword dw of the chunk at permuted position q
+            const int row = q >> 2, c = (q & 3) ^ ((row >> 1) & 3);
+            return (glb_void *)(nw + row * kC + c * 8 + dw * 2);
+        };
+        const int q0 = wave * (kWChunks / kWaves);
+        __builtin_amdgcn_global_load_lds(src(q0 + lane, 0), (lds_void *)wb, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src(q0 + 64 + lane, 0), (lds_void *)(wb + 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src(q0 + 128 + (lane >> 2), lane & 3), (lds_void *)(wb + 2048), 4, 0, 0);
     }
-    float bb[2][4];
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bb[ct][i] = bg[ct * 16 + g * 4 + i];
+    if (PF) {
+        glb_f32 *pfg = (glb_f32 *)pf;
+        __builtin_amdgcn_global_load_lds((glb_void *)(pfg + sym_src(threadIdx.x, pf_sym)),
+                                         (lds_void *)(xs_stage + wave * 64), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds((glb_void *)(pfg + sym_src(threadIdx.x + kT, pf_sym)),
+                                         (lds_void *)(xs_stage + kT + wave * 64), 4, 0, 0);
+    }
     float ps[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
     // The wave's tiles are rows y0 + 4 k (k = 0..7, y0 = wave / 2) of one
     // column half; with the halo rows, the read of tap (dy, dx) of row
@@ -465,10 +507,12 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
                     if (k == kSide / 4 - 1 && y0 == 3)
                         *reinterpret_cast<lds_bf16x4 *>(obase + (4 * k - kSide) * kActRow + op[ct]) = v;
                 }
-                if (gout) *reinterpret_cast<glb_bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
+                if (GOUT) *reinterpret_cast<glb_bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
             }
         }
     }
+    // the loads to LDS above have landed before the caller's barrier
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     if (POOL) {
         // lanes n = 0..15 of a k-group hold the same 4 channels for different
         // pixels: fixed-order butterfly over n
@@ -484,6 +528,22 @@ __device__ __attribute__((noinline)) void conv_mfma(const __bf16 *__restrict__ i
     }
 }
 
+// The layer as a call (see above). Its body is inlined here from a function
+// with restrict-qualified pointers, so its memory accesses carry alias scopes:
+// with them the compiler can tell that the layer's LDS reads do not touch
+// what the loads to LDS are writing, and does not wait for those loads first.
+template <bool POOL, bool PF, bool GOUT>
+__device__ __attribute__((noinline)) void conv_mfma(const __bf16 *in_p, __bf16 *out_p, __bf16 *wbuf_p,
+                                                    const __bf16 *next_w, const float *bias, __bf16 *gout_p,
+                                                    float *pool_part, const float *pf, int pf_sym, float *xs_stage)
+{
+    conv_body<POOL, PF, GOUT>(in_p, out_p, wbuf_p, next_w, bias, gout_p, pool_part, pf, pf_sym, xs_stage);
+}
+
+// TRAIN: the activations stored for the backward pass (a.acts) and, when
+// a.sym is given, a symmetry per patch from it rather than symmetries
+// 0 .. n_sym - 1; the inference build reads and writes nothing else per pass.
+template <bool TRAIN>
 __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -501,22 +561,45 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
 
     // Patches are claimed one at a time (each workgroup starts with its own
     // index, then takes the next free one), so workgroups that start late --
-    // behind other work on the device -- simply take fewer patches.
+    // behind other work on the device -- simply take fewer patches. A
+    // workgroup claims its next patch when it starts a patch and reads the
+    // next pass's input during conv2 of the current one, so neither the
+    // atomic nor the input read waits in line with the layers.
     __shared__ int claimed;
     // conv2's weights into LDS before the first patch; each conv layer then
     // stages the next one's (conv4 stages conv2's for the next pass)
     for (int i = tid; i < kWChunks; i += kT)
         *reinterpret_cast<bf16x8 *>(wbuf + act_off(i >> 2, i & 3)) =
             *reinterpret_cast<const bf16x8 *>(a.wf + (i >> 2) * kC + (i & 3) * 8);
+    // the first pass's input, staged where conv2 stages the later ones (each
+    // thread reads back only what it wrote)
+    if (blockIdx.x < a.batch) {
+        const int s0 = TRAIN && a.sym ? (int)a.sym[blockIdx.x] : 0;
+        const float *lk0 = a.logk + (size_t)blockIdx.x * kPix;
+        xs[tid] = lk0[sym_src(tid, s0)];
+        xs[tid + kT] = lk0[sym_src(tid + kT, s0)];
+    }
+    // launch constants in registers: conv1's operands and the head's weights
+    // for this thread (hidden unit h = tid / 16 and inputs j, j + 16, j + 32)
+    const Conv1W c1w = conv1_weights(prm);
+    const int hh = tid >> 4, hj = tid & 15;
+    const float m1a = prm[oM1 + hh * kZ + hj], m1b = prm[oM1 + hh * kZ + hj + 16];
+    const float m1c = hj + 32 < kZ ? prm[oM1 + hh * kZ + min(hj + 32, kZ - 1)] : 0.0f;
+    const float c1h = prm[oC1 + hh], m2a = prm[oM2 + hh], m2b = prm[oM2 + kH + hh];
+    const float c2a = prm[oC2], c2b = prm[oC2 + 1];
     __syncthreads();
     for (int b = blockIdx.x; b < a.batch;) {
-        const float *lk = a.logk + (size_t)b * kPix;
         float acc0 = 0.0f, acc1 = 0.0f;  // averaged prediction (thread 0)
         float lo0 = INFINITY, hi0 = -INFINITY, lo1 = INFINITY, hi1 = -INFINITY;  // their range
         for (int t = 0; t < a.n_sym; ++t) {
-            const int sym = a.sym ? (int)a.sym[b] : t;
-            // ---- input under the symmetry, centring (FP32) ----
-            const float v0 = lk[sym_src(tid, sym)], v1 = lk[sym_src(tid + kT, sym)];
+            const int sym = TRAIN && a.sym ? (int)a.sym[b] : t;
+            // the next patch, claimed now and used after conv1; a wrapping
+            // increment (no wrap below 2^32 - 1), since the compiler's
+            // wave-level rewrite of an add would wait for the result at once
+            int nxt;
+            if (tid == 0 && t == 0) nxt = (int)atomicInc(reinterpret_cast<unsigned *>(a.next), 0xffffffffu);
+            // ---- input under the symmetry (staged), centring (FP32) ----
+            const float v0 = xs[tid], v1 = xs[tid + kT];
             const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
             const float x0 = v0 - m, x1 = v1 - m;
             xs[tid] = x0;
@@ -545,18 +628,30 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
             series_parallel(xs, tmp, head + kC + 1);
             if (a.stats && t == 0 && tid < 4) a.stats[8 * (size_t)b + 4 + tid] = head[kC + 1 + tid];
             // ---- conv1: 1 -> 32 channels on MFMA ----
-            __bf16 *g1 = a.acts ? a.acts + ((size_t)0 * a.batch + b) * kPix * kC : nullptr;
-            conv1_mfma(xs, bufA, prm, g1);
+            __bf16 *g1 = TRAIN ? a.acts + ((size_t)0 * a.batch + b) * kPix * kC : nullptr;
+            conv1_mfma(xs, bufA, c1w, g1);
+            if (tid == 0 && t == 0) claimed = (int)gridDim.x + nxt;
             __syncthreads();
+            // the next pass: this patch under the next symmetry, or the
+            // claimed patch (none past the batch)
+            const int bn = t + 1 < a.n_sym ? b : claimed;
+            const bool more = bn < a.batch;
+            // with no next pass, the current patch is read again and not used
+            const float *pf = a.logk + (size_t)(more ? bn : b) * kPix;
+            const int sn = t + 1 < a.n_sym ? (TRAIN && a.sym ? sym : t + 1)
+                                           : (TRAIN && a.sym && more ? (int)a.sym[bn] : 0);
             // ---- conv2..conv4 on MFMA ----
-            __bf16 *g2 = a.acts ? a.acts + ((size_t)1 * a.batch + b) * kPix * kC : nullptr;
-            __bf16 *g3 = a.acts ? a.acts + ((size_t)2 * a.batch + b) * kPix * kC : nullptr;
-            __bf16 *g4 = a.acts ? a.acts + ((size_t)3 * a.batch + b) * kPix * kC : nullptr;
-            conv_mfma<false>(bufA, bufB, wbuf, a.wf + 9 * kC * kC, prm + oB2, g2, pool_part);
+            __bf16 *g2 = TRAIN ? a.acts + ((size_t)1 * a.batch + b) * kPix * kC : nullptr;
+            __bf16 *g3 = TRAIN ? a.acts + ((size_t)2 * a.batch + b) * kPix * kC : nullptr;
+            __bf16 *g4 = TRAIN ? a.acts + ((size_t)3 * a.batch + b) * kPix * kC : nullptr;
+            conv_mfma<false, true, TRAIN>(bufA, bufB, wbuf, a.wf + 9 * kC * kC, prm + oB2, g2, pool_part, pf, sn,
+                                          xs);
             __syncthreads();
-            conv_mfma<false>(bufB, bufA, wbuf, a.wf + 2 * 9 * kC * kC, prm + oB3, g3, pool_part);
+            conv_mfma<false, false, TRAIN>(bufB, bufA, wbuf, a.wf + 2 * 9 * kC * kC, prm + oB3, g3, pool_part,
+                                           nullptr, 0, nullptr);
             __syncthreads();
-            conv_mfma<true>(bufA, nullptr, wbuf, a.wf, prm + oB4, g4, pool_part);  // stages conv2's for the next pass
+            // stages conv2's weights for the next pass
+            conv_mfma<true, false, TRAIN>(bufA, nullptr, wbuf, a.wf, prm + oB4, g4, pool_part, nullptr, 0, nullptr);
             __syncthreads();
             // ---- pooling and head (FP32) ----
             if (tid < kC) {
@@ -568,14 +663,16 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
             __syncthreads();
             {
                 // hidden unit h on 16 threads, each summing inputs k = j, j + 16, j + 32
-                const int h = tid >> 4, j = tid & 15;
+                const int j = hj;
                 float zh = 0.0f;
-                for (int k = j; k < kZ; k += 16) zh += prm[oM1 + h * kZ + k] * head[k];
+                zh += m1a * head[j];
+                zh += m1b * head[j + 16];
+                if (j + 32 < kZ) zh += m1c * head[j + 32];
 #pragma unroll
                 for (int off = 1; off < 16; off <<= 1) zh += __shfl_xor(zh, off, 64);
-                const float hval = fmaxf(zh + prm[oC1 + h], 0.0f);
-                float y0 = j == 0 ? prm[oM2 + h] * hval : 0.0f;
-                float y1 = j == 0 ? prm[oM2 + kH + h] * hval : 0.0f;
+                const float hval = fmaxf(zh + c1h, 0.0f);
+                float y0 = j == 0 ? m2a * hval : 0.0f;
+                float y1 = j == 0 ? m2b * hval : 0.0f;
 #pragma unroll
                 for (int off = 16; off < 64; off <<= 1) {
                     y0 += __shfl_xor(y0, off, 64);
@@ -593,8 +690,8 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
                         s0 += red3[w];
                         s1 += red3[kWaves + w];
                     }
-                    s0 += prm[oC2] + m;
-                    s1 += prm[oC2 + 1] + m;
+                    s0 += c2a + m;
+                    s1 += c2b + m;
                     // a transposed patch predicts (kyy, kxx) of the original
                     const float q0 = (sym & 1) ? s1 : s0, q1 = (sym & 1) ? s0 : s1;
                     acc0 += q0;
@@ -614,11 +711,9 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
                 a.spread[2 * (size_t)b] = hi0 - lo0;
                 a.spread[2 * (size_t)b + 1] = hi1 - lo1;
             }
-            claimed = (int)gridDim.x + atomicAdd(a.next, 1);
         }
-        // every thread reads the claim before the next write to it, which
-        // comes after the barriers of the next patch
-        __syncthreads();
+        // written after conv1 of this patch's first pass; the next write
+        // comes after the barriers of the next patch's first pass
         b = claimed;
     }
 }
@@ -1006,10 +1101,16 @@ lbm_status forward(const float *prm, int batch, const float *logk, const int8_t 
     a.acts = train ? reinterpret_cast<__bf16 *>(ws + L.off_acts) : nullptr;
     a.pool_out = train ? reinterpret_cast<float *>(ws + L.off_pool) : nullptr;
     a.next = reinterpret_cast<int *>(ws + L.off_next);
-    LBM_HIP(hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdLds));
+    LBM_HIP(hipFuncSetAttribute((const void *)k_forward<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kFwdLds));
+    LBM_HIP(hipFuncSetAttribute((const void *)k_forward<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kFwdLds));
     const int cap = max_workgroups > 0 ? std::min(max_workgroups, device_cu_count()) : device_cu_count();
     const int grid = std::max(1, std::min(batch, cap));
-    hipLaunchKernelGGL(k_forward, dim3(grid), dim3(kT), kFwdLds, stream, a);
+    if (train)
+        hipLaunchKernelGGL(k_forward<true>, dim3(grid), dim3(kT), kFwdLds, stream, a);
+    else
+        hipLaunchKernelGGL(k_forward<false>, dim3(grid), dim3(kT), kFwdLds, stream, a);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
