@@ -372,7 +372,6 @@ __device__ __forceinline__ void conv_body(const __bf16 *__restrict__ in_p, __bf1
                                           float *__restrict__ pool_part, const float *__restrict__ pf, int pf_sym,
                                           float *__restrict__ xs_stage)
 {
-    constexpr int U = 1;  // tiles per iteration (2: more registers, callee-saved spills, slower)
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
     typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
@@ -451,64 +450,70 @@ __device__ __forceinline__ void conv_body(const __bf16 *__restrict__ in_p, __bf1
                                          (lds_void *)(xs_stage + kT + wave * 64), 4, 0, 0);
     }
     float ps[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    // The wave's tiles are rows y0 + 4 k (k = 0..7, y0 = wave / 2) of one
-    // column half; with the halo rows, the read of tap (dy, dx) of row
-    // y0 + 4 k is at base[dx] + (4 k + dy) rows, a compile-time offset.
-    const int y0 = wave >> 1;
+    // The wave's tiles are the 8 consecutive rows r0 .. r0 + 7 (r0 = 8 x
+    // (wave / 2)) of one column half. The input rows r0 - 1 .. r0 + 8 (halo
+    // rows included) are read once each, three reads (dx = -1, 0, 1), and
+    // each feeds the up to three output rows it is a tap row of, whose
+    // accumulators roll through three slots: a third of the LDS reads of
+    // reading nine operands per tile. Every tile still adds its taps in the
+    // order t = 0..8. The epilogue of a row runs once its last tap row is in.
+    const int r0 = (wave >> 1) * 8;
     const lds_bf16 *base[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) base[d] = in + y0 * kActRow + colp[d];
-    lds_bf16 *obase = out + y0 * kActRow;
-#pragma unroll 1
-    for (int it = 0; it < kPix / 16 / (U * kWaves); ++it) {
-        f32x4 acc[U][2];
+    for (int d = 0; d < 3; ++d) base[d] = in + r0 * kActRow + colp[d];
+    lds_bf16 *obase = out + r0 * kActRow;
+    constexpr int kRows = 8;
+    f32x4 acc[3][2];
+    auto epilogue = [&](int k, const f32x4 (&ac)[2]) {
+        const int y = r0 + k;
+        const int p = y * kSide + col0;  // D column = pixel
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int ct = 0; ct < 2; ++ct) {
+            bf16x4 v;
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) acc[u][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-        bf16x8 xb[9][U];
-#pragma unroll
-        for (int t = 0; t < 9; ++t)
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                xb[t][u] = *reinterpret_cast<const lds_bf16x8 *>(
-                    base[tap_dx(t) + 1] + (4 * (it * U + u) + tap_dy(t)) * kActRow);
-        // all reads of the iteration are issued before its first MFMA (left
-        // to itself the scheduler reuses one register and waits on each read)
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                acc[u][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][0], xb[t][u], acc[u][0], 0, 0, 0);
-                acc[u][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][1], xb[t][u], acc[u][1], 0, 0, 0);
+            for (int i = 0; i < 4; ++i) {
+                const float r = fmaxf(ac[ct][i] + bb[ct][i], 0.0f);
+                if (POOL) ps[ct][i] += r;
+                v[i] = (__bf16)r;
             }
+            if (!POOL) {
+                *reinterpret_cast<lds_bf16x4 *>(obase + k * kActRow + op[ct]) = v;
+                // rows 0 and 31 also go to their halo copies (uniform over the wave)
+                if (k == 0 && r0 == 0) *reinterpret_cast<lds_bf16x4 *>(obase + kSide * kActRow + op[ct]) = v;
+                if (k == kRows - 1 && r0 == kSide - kRows)
+                    *reinterpret_cast<lds_bf16x4 *>(obase + (k - kSide) * kActRow + op[ct]) = v;
+            }
+            if (GOUT) *reinterpret_cast<glb_bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
         }
+    };
+    bf16x8 x[2][3];  // the operands of input rows i and i + 1
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = it * U + u;
-            const int y = y0 + 4 * k;
-            const int p = y * kSide + col0;  // D column = pixel
+    for (int d = 0; d < 3; ++d) x[0][d] = *reinterpret_cast<const lds_bf16x8 *>(base[d] - kActRow);
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-                bf16x4 v;
+    for (int i = 0; i < kRows + 2; ++i) {  // input row r0 - 1 + i
+        const int cur = i & 1;
+        // one row ahead only (hoisting every read to the top would need
+        // registers for all of them)
+        __builtin_amdgcn_sched_barrier(0);
+        if (i + 1 < kRows + 2) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float r = fmaxf(acc[u][ct][i] + bb[ct][i], 0.0f);
-                    if (POOL) ps[ct][i] += r;
-                    v[i] = (__bf16)r;
-                }
-                if (!POOL) {
-                    *reinterpret_cast<lds_bf16x4 *>(obase + 4 * k * kActRow + op[ct]) = v;
-                    // rows 0 and 31 also go to their halo copies: k = 0 with
-                    // y0 = 0 and k = 7 with y0 = 3 (uniform over the wave)
-                    if (k == 0 && y0 == 0)
-                        *reinterpret_cast<lds_bf16x4 *>(obase + kSide * kActRow + op[ct]) = v;
-                    if (k == kSide / 4 - 1 && y0 == 3)
-                        *reinterpret_cast<lds_bf16x4 *>(obase + (4 * k - kSide) * kActRow + op[ct]) = v;
-                }
-                if (GOUT) *reinterpret_cast<glb_bf16x4 *>(gout + p * kC + ct * 16 + g * 4) = v;
+            for (int d = 0; d < 3; ++d)
+                x[cur ^ 1][d] = *reinterpret_cast<const lds_bf16x8 *>(base[d] + i * kActRow);
+        }
+        // output rows k = i (tap row dy = -1), i - 1 (dy = 0), i - 2 (dy = 1)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int k = i - 1 - dy;
+            if (k < 0 || k >= kRows) continue;
+            f32x4 (&ac)[2] = acc[k % 3];
+            if (dy == -1) ac[0] = ac[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int t = 3 * (dy + 1) + d;
+                ac[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][0], x[cur][d], ac[0], 0, 0, 0);
+                ac[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[t][1], x[cur][d], ac[1], 0, 0, 0);
             }
+            if (dy == 1) epilogue(k, ac);
         }
     }
     // the loads to LDS above have landed before the caller's barrier
