@@ -5,7 +5,7 @@
 // patch to log K_eff (xx and yy), the quantity the local problems of Sec. 3
 // compute with Eq. tensor-kappa:
 //   m = mean(log K), x = log K - m                    (FP32)
-//   a1 = relu(conv3x3(x))      1 -> 32 channels      (BF16 MFMA, the 9 taps as K)
+//   a1 = relu(conv3x3(x))      1 -> 32 channels      (BF16 MFMA, the 9 taps and zeros as K = 16)
 //   a2..a4 = relu(conv3x3(.))  32 -> 32 channels     (BF16 MFMA, FP32 accumulate)
 //   p = mean over pixels of a4                       (FP32)
 //   s = log series/parallel estimates of exp(x)      (FP32, 4 values:
@@ -119,6 +119,31 @@ __device__ __forceinline__ int sym_src(int p, int sym)
     return v * kSide + u;
 }
 
+// Sums over 8- and 16-lane groups with DPP lane moves (no LDS permutes):
+// within a quad the moves pair lanes i and i ^ 1, then i ^ 2; the mirrors
+// then pair each lane with one of the other half of its 8- or 16-lane group,
+// which holds the same value as lane i ^ 4 (i ^ 8) once the halves are
+// reduced, so the sums are bit for bit those of a xor butterfly over 1, 2,
+// 4 (and 8).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float group_sum8(float v)
+{
+    v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    return v;
+}
+__device__ __forceinline__ float group_sum16(float v)
+{
+    v = group_sum8(v);
+    v += dpp_mov<0x140>(v);  // row_mirror
+    return v;
+}
+
 // The four series/parallel features of k = exp(x) from the centred patch in
 // LDS, on all 512 threads: 8 threads per line (lines 0..31 rows, 32..63
 // columns) each sum 1/k and k over 4 pixels; fixed-order butterflies give
@@ -136,15 +161,14 @@ __device__ __forceinline__ void series_parallel(const float *xs, float *lane_tmp
         hs += __expf(-x);
         as += __expf(x);
     }
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-        hs += __shfl_xor(hs, off, 64);
-        as += __shfl_xor(as, off, 64);
-    }
+    hs = group_sum8(hs);
+    as = group_sum8(as);
     float h = kSide / hs;   // harmonic mean of the line
     float ia = kSide / as;  // 1 / arithmetic mean of the line
+    h += dpp_mov<0x140>(h);  // the 8-lane groups are uniform: the mirror pairs as i ^ 8 does
+    ia += dpp_mov<0x140>(ia);
 #pragma unroll
-    for (int off = 8; off < 64; off <<= 1) {
+    for (int off = 16; off < 64; off <<= 1) {
         h += __shfl_xor(h, off, 64);
         ia += __shfl_xor(ia, off, 64);
     }
@@ -218,27 +242,28 @@ __device__ __forceinline__ void block_sum3_fixed(float &a, float &b, float &c, f
 // conv1's A operands (W1 with the taps as K, zero beyond tap 8) and its bias
 // as this lane needs them. Loaded once per launch: read at every patch, the
 // sixteen guarded loads each waited for their own round trip to L2.
+typedef short s16x4 __attribute__((ext_vector_type(4)));  // four BF16 as the 16x16x16 MFMA takes them
 struct Conv1W {
-    bf16x8 w0, w1;
+    s16x4 w0, w1;
     float b0[4], b1[4];
 };
 __device__ __forceinline__ Conv1W conv1_weights(const float *__restrict__ prm)
 {
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
-    float v0[8], v1[8];
+    float v0[4], v1[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {  // unconditional reads (tap clamped), so all are in flight together
-        const int t = min(g * 8 + j, 8);
+    for (int j = 0; j < 4; ++j) {  // unconditional reads (tap clamped), so all are in flight together
+        const int t = min(g * 4 + j, 8);
         v0[j] = prm[oW1 + t * kC + n];
         v1[j] = prm[oW1 + t * kC + 16 + n];
     }
     Conv1W c;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const bool tap = g * 8 + j < 9;
-        c.w0[j] = (__bf16)(tap ? v0[j] : 0.0f);
-        c.w1[j] = (__bf16)(tap ? v1[j] : 0.0f);
+    for (int j = 0; j < 4; ++j) {
+        const bool tap = g * 4 + j < 9;
+        c.w0[j] = __builtin_bit_cast(short, (__bf16)(tap ? v0[j] : 0.0f));
+        c.w1[j] = __builtin_bit_cast(short, (__bf16)(tap ? v1[j] : 0.0f));
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -255,35 +280,36 @@ __device__ __forceinline__ void conv1_mfma(const float *__restrict__ xs, __bf16 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = lane & 15, g = lane >> 4;  // n: output channel row of A / pixel of B; g: k-group
-    const bf16x8 w0 = cw.w0, w1 = cw.w1;
+    const s16x4 w0 = cw.w0, w1 = cw.w1;
     const float *b0 = cw.b0, *b1 = cw.b1;
     // Every tile of this wave has the same column half (kWaves is even), so
     // the offset of tap j from the tile's row start, wrapped in x, is fixed
     // per lane; the row wrap is the wrap of the whole 1024-pixel plane.
     // Padded taps (t >= 9) read the centre pixel; their weights are zero.
+    // K = 16 (the nine taps and zeros): four taps per lane.
     static_assert(kWaves % 2 == 0, "the column half of a wave's tiles must not change");
     const int x0 = (wave & 1) * 16;
-    int off[8];
+    int off[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int t = g * 8 + j;
+    for (int j = 0; j < 4; ++j) {
+        const int t = g * 4 + j;
         const int tt = t < 9 ? t : 4;
         off[j] = tap_dy(tt) * kSide + wrap32(x0 + n + tap_dx(tt));  // rows -1 and 32 are xs's halo
     }
-    // two tiles per iteration, all sixteen reads issued before either MFMA
+    // two tiles per iteration, all eight reads issued before either MFMA
     for (int tile = wave; tile < kPix / 16; tile += 2 * kWaves) {
-        bf16x8 a[2];
+        s16x4 a[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int ybase = ((tile + u * kWaves) >> 1) * kSide;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) a[u][j] = (__bf16)xs[ybase + off[j]];
+            for (int j = 0; j < 4; ++j) a[u][j] = __builtin_bit_cast(short, (__bf16)xs[ybase + off[j]]);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-            const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, a[u], z, 0, 0, 0);
-            const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, a[u], z, 0, 0, 0);
+            const f32x4 acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w0, a[u], z, 0, 0, 0);
+            const f32x4 acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1, a[u], z, 0, 0, 0);
             const int y = (tile + u * kWaves) >> 1;
             const int p = y * kSide + x0 + n;  // D column = pixel
             bf16x4 v0, v1;
@@ -525,9 +551,7 @@ __device__ __forceinline__ void conv_body(const __bf16 *__restrict__ in_p, __bf1
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float v = ps[ct][i];
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
+                const float v = group_sum16(ps[ct][i]);
                 if (n == 0) pool_part[wave * kC + ct * 16 + g * 4 + i] = v;
             }
     }
@@ -673,8 +697,7 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
                 zh += m1a * head[j];
                 zh += m1b * head[j + 16];
                 if (j + 32 < kZ) zh += m1c * head[j + 32];
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) zh += __shfl_xor(zh, off, 64);
+                zh = group_sum16(zh);
                 const float hval = fmaxf(zh + c1h, 0.0f);
                 float y0 = j == 0 ? m2a * hval : 0.0f;
                 float y1 = j == 0 ? m2b * hval : 0.0f;
