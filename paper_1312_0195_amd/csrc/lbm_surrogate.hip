@@ -143,6 +143,31 @@ __device__ __forceinline__ float group_sum16(float v)
     v += dpp_mov<0x140>(v);  // row_mirror
     return v;
 }
+// A xor butterfly over the wave in the order 32, 16, 8, 4, 2, 1, bit for bit:
+// the two steps across 16-lane rows as lane permutes, then a rotation of
+// each row by 8 (lane i gets lane i ^ 8), by 4 (the row now repeats every 8
+// lanes, so i + 4 has the value of i ^ 4), and the quad moves.
+__device__ __forceinline__ float wave_sum_desc(float v)
+{
+    v += __shfl_xor(v, 32, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += dpp_mov<0x128>(v);  // row_ror:8
+    v += dpp_mov<0x124>(v);  // row_ror:4
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0xB1>(v);
+    return v;
+}
+// Lane 0's value of a xor butterfly over 16 and 32 when every 16-lane row
+// is uniform (or only the first lane of each row counts): (row 0 + row 1) +
+// (row 2 + row 3), read from lanes 0, 16, 32, 48.
+__device__ __forceinline__ float rows_sum_lane0(float v)
+{
+    const int b = __builtin_bit_cast(int, v);
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 48));
+    return (v + r1) + (r2 + r3);
+}
 
 // The four series/parallel features of k = exp(x) from the centred patch in
 // LDS, on all 512 threads: 8 threads per line (lines 0..31 rows, 32..63
@@ -167,11 +192,8 @@ __device__ __forceinline__ void series_parallel(const float *xs, float *lane_tmp
     float ia = kSide / as;  // 1 / arithmetic mean of the line
     h += dpp_mov<0x140>(h);  // the 8-lane groups are uniform: the mirror pairs as i ^ 8 does
     ia += dpp_mov<0x140>(ia);
-#pragma unroll
-    for (int off = 16; off < 64; off <<= 1) {
-        h += __shfl_xor(h, off, 64);
-        ia += __shfl_xor(ia, off, 64);
-    }
+    h = rows_sum_lane0(h);  // lane 0 writes the wave's value below
+    ia = rows_sum_lane0(ia);
     const int wave = tid >> 6;
     if ((tid & 63) == 0) {
         lane_tmp[wave] = h;
@@ -194,8 +216,7 @@ __device__ __forceinline__ void series_parallel(const float *xs, float *lane_tmp
 __device__ __forceinline__ float block_sum_fixed(float v, float *red)
 {
     // fixed-order sum over the workgroup: wave butterflies, then wave partials
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum_desc(v);
     const int tid = threadIdx.x;
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -208,12 +229,9 @@ __device__ __forceinline__ float block_sum_fixed(float v, float *red)
 // Three fixed-order workgroup sums with one pair of barriers; red: 3 x kWaves.
 __device__ __forceinline__ void block_sum3_fixed(float &a, float &b, float &c, float *red)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-        c += __shfl_xor(c, off, 64);
-    }
+    a = wave_sum_desc(a);
+    b = wave_sum_desc(b);
+    c = wave_sum_desc(c);
     const int tid = threadIdx.x;
     __syncthreads();
     if ((tid & 63) == 0) {
@@ -369,14 +387,10 @@ struct FwdArgs {
 // W[co][ci] X[ci][pixel] per tap (A: weights, held in registers; B: 8
 // channels of one pixel per lane, one 16-byte LDS read), so each lane ends
 // with 4 consecutive output channels of one pixel and stores them with one
-// 8-byte write. Each wave takes its eight 16-pixel tiles one at a time: the
-// nine operand reads of a tile are issued together, then its 18 MFMAs (two
-// accumulation chains, one per 16-channel half). The layer is bound by
-// instruction issue more than by LDS latency: cheap addressing (below) gained
-// 1.25x, while deeper read pipelines gained little or nothing. With POOL the
-// ReLU outputs are summed per channel into pool_part[wave][32] instead of
-// being stored. Not inlined: inlined into k_forward, its live registers
-// spilled to scratch; as a call the layer has the register file to itself.
+// 8-byte write. Each wave takes eight 16-pixel tiles, the consecutive rows of
+// one column half, reading each input row once for the three output rows it
+// feeds (below). With POOL the ReLU outputs are summed per channel into
+// pool_part[wave][32] instead of being stored.
 // Address-space-qualified element types: a generic pointer makes the
 // compiler emit flat memory instructions, which count against the LDS wait
 // counter too, so every MFMA would wait for all LDS reads in flight.
@@ -557,14 +571,15 @@ __device__ __forceinline__ void conv_body(const __bf16 *__restrict__ in_p, __bf1
     }
 }
 
-// The layer as a call (see above). Its body is inlined here from a function
-// with restrict-qualified pointers, so its memory accesses carry alias scopes:
+// The layer as the kernel inlines it. Its body comes from a function with
+// restrict-qualified pointers, so its memory accesses carry alias scopes:
 // with them the compiler can tell that the layer's LDS reads do not touch
 // what the loads to LDS are writing, and does not wait for those loads first.
+// (As a call, the layer paid a full wait at entry and register saves.)
 template <bool POOL, bool PF, bool GOUT>
-__device__ __attribute__((noinline)) void conv_mfma(const __bf16 *in_p, __bf16 *out_p, __bf16 *wbuf_p,
-                                                    const __bf16 *next_w, const float *bias, __bf16 *gout_p,
-                                                    float *pool_part, const float *pf, int pf_sym, float *xs_stage)
+__device__ __forceinline__ void conv_mfma(const __bf16 *in_p, __bf16 *out_p, __bf16 *wbuf_p, const __bf16 *next_w,
+                                          const float *bias, __bf16 *gout_p, float *pool_part, const float *pf,
+                                          int pf_sym, float *xs_stage)
 {
     conv_body<POOL, PF, GOUT>(in_p, out_p, wbuf_p, next_w, bias, gout_p, pool_part, pf, pf_sym, xs_stage);
 }
@@ -699,13 +714,9 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
                 if (j + 32 < kZ) zh += m1c * head[j + 32];
                 zh = group_sum16(zh);
                 const float hval = fmaxf(zh + c1h, 0.0f);
-                float y0 = j == 0 ? m2a * hval : 0.0f;
-                float y1 = j == 0 ? m2b * hval : 0.0f;
-#pragma unroll
-                for (int off = 16; off < 64; off <<= 1) {
-                    y0 += __shfl_xor(y0, off, 64);
-                    y1 += __shfl_xor(y1, off, 64);
-                }
+                // the first lane of each 16-lane row holds its unit's terms
+                const float y0 = rows_sum_lane0(j == 0 ? m2a * hval : 0.0f);
+                const float y1 = rows_sum_lane0(j == 0 ? m2b * hval : 0.0f);
                 if ((tid & 63) == 0) {
                     red3[tid >> 6] = y0;
                     red3[kWaves + (tid >> 6)] = y1;
