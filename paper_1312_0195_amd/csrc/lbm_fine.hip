@@ -71,6 +71,7 @@ struct StepArgs {
 template <typename A, typename R>
 struct Kc {
     A om, omc, twotau, omtt, hegx, hegy, rho0;
+    A hegx2, hegy2;  // 2 hegx, 2 hegy (exact)
     __device__ explicit Kc(const StepArgs<R> &a)
     {
         if constexpr (sizeof(A) == 8) {
@@ -80,6 +81,8 @@ struct Kc {
             om = (A)a.om; omc = (A)a.omc; twotau = (A)a.twotau; omtt = (A)a.omtt;
             hegx = (A)a.hegx; hegy = (A)a.hegy; rho0 = (A)a.rho0;
         }
+        hegx2 = hegx + hegx;
+        hegy2 = hegy + hegy;
     }
 };
 
@@ -280,7 +283,11 @@ struct LdsCoef {
 // PK: 1 scalar drag deficit E = 1 - D, 4 tensor I - M (Shan-Chen form); 0 the Guo
 // form with coef = eps nu / kappa. Coefficients come from cm at index c, the
 // per-cell force from fm at index cf.
-template <typename R, int PK, bool FF, class CM, class FM, typename A>
+// E2 (FP32 arithmetic, scalar drag): cm gives 2E, so the exact factor 2 of
+// om rho u_eq is folded into the coefficient (2 fma(-E, h, g) = fma(-2E, h,
+// 2g) exactly). GY false: no drive along y (hegy = 0), so hy = jy and the
+// y terms of g vanish; om rho u_eq is bit for bit the same either way.
+template <typename R, int PK, bool FF, bool E2 = false, bool GY = true, class CM, class FM, typename A>
 __device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, int cf, const CM &cm,
                                           const FM &fm)
 {
@@ -350,18 +357,26 @@ __device__ __forceinline__ void collide_m(const StepArgs<R> &a, A f[9], int c, i
         //    so all kernels that inline this (interior and edge paths, one and
         //    several steps per launch) round alike.
 #pragma clang fp contract(off)
-        A tx, ty;  // eps rho G / 2 - E h
-        if (PK == 1) {
+        // h = j + eps rho G / 2 with one rounding (g x rho fused into the sum)
+        const A gcx = FF ? (A)fm.ld(0, cf) : k.hegx, gcy = FF ? (A)fm.ld(1, cf) : k.hegy;
+        const A hxf = __builtin_fmaf(gcx, rho, jx), hyf = __builtin_fmaf(gcy, rho, jy);
+        A tx, ty;  // 2 (eps rho G / 2 - E h)
+        if constexpr (PK == 1 && E2) {
+            static_assert(!FF, "the doubled coefficient is for a uniform drive");
+            const A e2 = (A)cm.ld(0, c);  // 2E
+            tx = __builtin_fmaf(-e2, hxf, k.hegx2 * rho);
+            ty = GY ? __builtin_fmaf(-e2, hyf, k.hegy2 * rho) : -e2 * jy;
+        } else if constexpr (PK == 1) {
             const A e = (A)cm.ld(0, c);
-            tx = __builtin_fmaf(-e, hx, gx);
-            ty = __builtin_fmaf(-e, hy, gy);
+            tx = (A)2 * __builtin_fmaf(-e, hxf, gcx * rho);
+            ty = (A)2 * __builtin_fmaf(-e, hyf, gcy * rho);
         } else {
             const A e00 = cm.ld(0, c), e01 = cm.ld(1, c);
             const A e10 = cm.ld(2, c), e11 = cm.ld(3, c);
-            tx = gx - __builtin_fmaf(e00, hx, e01 * hy);
-            ty = gy - __builtin_fmaf(e10, hx, e11 * hy);
+            tx = (A)2 * (gcx * rho - __builtin_fmaf(e00, hxf, e01 * hyf));
+            ty = (A)2 * (gcy * rho - __builtin_fmaf(e10, hxf, e11 * hyf));
         }
-        const A Mx = __builtin_fmaf(om, jx, (A)2 * tx), My = __builtin_fmaf(om, jy, (A)2 * ty);
+        const A Mx = __builtin_fmaf(om, jx, tx), My = __builtin_fmaf(om, jy, ty);
         const A D = om * dr;
         const A b = D * (A)(1.0 / 9.0);
         const A cc = D * (A)(1.0 / 36.0);
@@ -475,7 +490,7 @@ template <> struct TileDA<float, 2, float> : TileShape<LBM_TILE2F> {};
 // one-step launches while HBM sees one read and one write of the state per D
 // steps (plus the halo, which neighbouring tiles mostly find in L2). Loads and
 // stores go through BMem (32-bit offsets, plane bases in scalar registers).
-template <typename R, bool WALLS, int PK, bool FF, int D, typename A = double>
+template <typename R, bool WALLS, int PK, bool FF, int D, typename A = double, bool GY = true>
 __global__ __launch_bounds__((TileDA<R, D, A>::BS)) void k_stepd(StepArgs<R> a)
 {
     constexpr int TX = TileDA<R, D, A>::TX, TY = TileDA<R, D, A>::TY, BS = TileDA<R, D, A>::BS;
@@ -485,6 +500,9 @@ __global__ __launch_bounds__((TileDA<R, D, A>::BS)) void k_stepd(StepArgs<R> a)
     // scalar coefficients without a force field are read once from HBM and
     // kept in LDS next to the populations
     constexpr bool CL = (PK != 4) && !FF && 10 * AN * sizeof(R) <= 160 * 1024;
+    // FP32 arithmetic keeps 2E there (the exact factor 2 of the collision)
+    constexpr bool E2 = CL && PK == 1 && sizeof(A) == 4 && sizeof(R) == 4;
+    static_assert(GY || E2, "the variant without a y drive is the FP32 scalar one");
     __shared__ R P[9][AN];
     __shared__ R Dl[CL ? AN : 1];
     const int nx = a.nx, ny = a.ny;
@@ -562,9 +580,10 @@ __global__ __launch_bounds__((TileDA<R, D, A>::BS)) void k_stepd(StepArgs<R> a)
 #pragma unroll
             for (int q = 0; q < 9; ++q) f[q] = (A)fr[q];
             if constexpr (CL) {
-                const R d = BMem<R>{a.coef, nullptr, a.cstride}.ld(0, y * nx + x);
+                const R d0 = BMem<R>{a.coef, nullptr, a.cstride}.ld(0, y * nx + x);
+                const R d = E2 ? d0 + d0 : d0;
                 Dl[i] = d;
-                collide_m<R, PK, FF>(a, f, 0, 0, OneCoef<R>{d}, OneCoef<R>{d});
+                collide_m<R, PK, FF, E2, GY>(a, f, 0, 0, OneCoef<R>{d}, OneCoef<R>{d});
             } else {
                 collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
             }
@@ -607,7 +626,7 @@ __global__ __launch_bounds__((TileDA<R, D, A>::BS)) void k_stepd(StepArgs<R> a)
                     for (int q = 0; q < 9; ++q) f[q] = (A)pr[k][q];
                     const int c = py * AX + px;
                     if constexpr (CL)
-                        collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
+                        collide_m<R, PK, FF, E2, GY>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
                     else
                         collide_cell<R, PK, FF, BMem<R>>(a, f, y * nx + x);
 #pragma unroll
@@ -626,7 +645,7 @@ __global__ __launch_bounds__((TileDA<R, D, A>::BS)) void k_stepd(StepArgs<R> a)
             pull_lds(c, y, !FAST, f);
             const int g = y * nx + x;
             if constexpr (CL)
-                collide_m<R, PK, FF>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
+                collide_m<R, PK, FF, E2, GY>(a, f, c, c, LdsCoef<R>{Dl}, LdsCoef<R>{Dl});
             else
                 collide_cell<R, PK, FF, BMem<R>>(a, f, g);
 #pragma unroll
@@ -1019,8 +1038,15 @@ struct StepDFn {
             if (h->p.pop_dtype == LBM_F32_FAST) {
                 using TF = TileDA<R, D, float>;
                 const int fx = (h->p.nx + TF::TX - 1) / TF::TX, fy = (h->p.ny + TF::TY - 1) / TF::TY;
-                hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D, float>), dim3(fx * fy), dim3(TF::BS), 0, h->stream,
-                                   step_args<R>(h));
+                const StepArgs<R> sa = step_args<R>(h);
+                if constexpr (PK == 1 && !FF) {
+                    if ((float)sa.hegy == 0.0f) {  // drive along x only
+                        hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D, float, false>), dim3(fx * fy), dim3(TF::BS), 0,
+                                           h->stream, sa);
+                        return;
+                    }
+                }
+                hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D, float>), dim3(fx * fy), dim3(TF::BS), 0, h->stream, sa);
                 return;
             }
         }
