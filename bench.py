@@ -610,7 +610,7 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "frac_of_unpacked_fp32": round(achieved / FP32_UNPACKED_TFLOPS, 4),
                      "traffic": traffic,
-                     "kernel": f"k_stepd<float, walls, scalar, no force field, {DEPTH}, float> ({DEPTH} time steps per launch, FP32 arithmetic)",
+                     "kernel": f"k_stepd<float, walls, scalar, no force field, {DEPTH}, float, no y drive> ({DEPTH} time steps per launch, FP32 arithmetic)",
                      "avg_launch_us": round(step_ms * 1e3, 3),
                      "launches_timed": KERNEL_LAUNCHES,
                      "warmup_launches": KERNEL_WARMUP_LAUNCHES,
