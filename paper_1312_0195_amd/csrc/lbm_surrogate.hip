@@ -27,10 +27,12 @@
 // batch. Activations stay in LDS ([pixel][channel] BF16 with the channel
 // chunks of each pixel permuted (act_off), 64 KB per layer plus halo rows,
 // two buffers), and the BF16 weights of the 32 -> 32 layers pass through an
-// 18 KB LDS buffer, one layer ahead; a 16x16x32 MFMA takes 16 pixels x 32
-// input channels of one tap, so a 3x3 layer is 9 MFMAs per 16-pixel x
-// 16-channel output tile. The last conv layer is pooled straight from the
-// accumulators.
+// 18 KB LDS buffer, one layer ahead, loaded from global memory straight into
+// LDS while a layer runs (as is the next pass's input); a 16x16x32 MFMA takes
+// 16 pixels x 32 input channels of one tap, so a 3x3 layer is 9 MFMAs per
+// 16-pixel x 16-channel output tile, and each wave reads every input row of
+// its eight output rows once. No global read is waited for in line with the
+// layers. The last conv layer is pooled straight from the accumulators.
 //
 // Training: the forward also stores a1..a4 (BF16) and the pooled features;
 // the head backward runs per patch in FP32; the conv backward walks layers
