@@ -609,6 +609,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "frac_of_unpacked_fp32": round(achieved / FP32_UNPACKED_TFLOPS, 4),
+                     "peak_note": "the published FP32 vector rate counts packed FP32 FMAs; the "
+                                  "kernels are built without packed FP32, whose instruction-rate "
+                                  "ceiling is half that (frac_of_unpacked_fp32)",
                      "traffic": traffic,
                      "kernel": f"k_stepd<float, walls, scalar, no force field, {DEPTH}, float, no y drive> ({DEPTH} time steps per launch, FP32 arithmetic)",
                      "avg_launch_us": round(step_ms * 1e3, 3),
