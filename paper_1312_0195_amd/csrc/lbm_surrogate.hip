@@ -612,6 +612,10 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
     // next pass's input during conv2 of the current one, so neither the
     // atomic nor the input read waits in line with the layers.
     __shared__ int claimed;
+    // The patch mean and its four series/parallel features do not depend on
+    // the symmetry a pass applies (a transposition exchanges the row and
+    // column features): passes after the first take them from here.
+    __shared__ float pass0[5];
     // conv2's weights into LDS before the first patch; each conv layer then
     // stages the next one's (conv4 stages conv2's for the next pass)
     for (int i = tid; i < kWChunks; i += kT)
@@ -646,7 +650,7 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
             if (tid == 0 && t == 0) nxt = (int)atomicInc(reinterpret_cast<unsigned *>(a.next), 0xffffffffu);
             // ---- input under the symmetry (staged), centring (FP32) ----
             const float v0 = xs[tid], v1 = xs[tid + kT];
-            const float m = block_sum_fixed(v0 + v1, red) * (1.0f / kPix);
+            const float m = t == 0 ? block_sum_fixed(v0 + v1, red) * (1.0f / kPix) : pass0[0];
             const float x0 = v0 - m, x1 = v1 - m;
             xs[tid] = x0;
             xs[tid + kT] = x1;
@@ -671,8 +675,14 @@ __global__ __launch_bounds__(kT) void k_forward(FwdArgs a)
                     st[3] = var > 0.f ? cy / var : 0.f;
                 }
             }
-            series_parallel(xs, tmp, head + kC + 1);
-            if (a.stats && t == 0 && tid < 4) a.stats[8 * (size_t)b + 4 + tid] = head[kC + 1 + tid];
+            if (t == 0) {
+                series_parallel(xs, tmp, head + kC + 1);
+                if (a.stats && tid < 4) a.stats[8 * (size_t)b + 4 + tid] = head[kC + 1 + tid];
+                if (tid < 5) pass0[tid] = tid == 0 ? m : head[kC + tid];
+            } else if (tid < 4) {
+                // features 0, 1 along rows and columns, 2, 3 along columns and rows
+                head[kC + 1 + tid] = pass0[1 + ((sym & 1) ? tid ^ 2 : tid)];
+            }
             // ---- conv1: 1 -> 32 channels on MFMA ----
             __bf16 *g1 = TRAIN ? a.acts + ((size_t)0 * a.batch + b) * kPix * kC : nullptr;
             conv1_mfma(xs, bufA, c1w, g1);
