@@ -314,11 +314,45 @@ def bench_coarse(L, torch, keff, r=32, reps=3):
                 mlups=round(ncx * ncy * steps / best / 1e6, 1))
 
 
-def bench_surrogate(n_test=65536):
+def cpu_baseline_surrogate(big, x0, y0, every=512):
+    """The oracle's local problems on a bounded sample of the surrogate's test
+    patches (every `every`-th 32 x 32 patch, both drives, the labels'
+    tolerance of 1e-7 per 100 steps), items spread over host threads as in
+    cpu_baseline_local: the LBM-only rate the surrogate path replaces."""
+    import concurrent.futures as cf
+    from oracle import oracle as O
+    from paper_1312_0195_amd import inputs as I
+    from paper_1312_0195_amd import surrogate as S
+    threads = min(os.cpu_count() or 1, 16)
+    ph = S.PHYS
+
+    def solve(args):
+        O.set_threads(1)
+        a, b = args
+        return O.local_keff(I.cut_patch(big, a, b, S.SIDE), ph["tau"], ph["eps"], ph["nu"], ph["g"],
+                            check_every=100, tol=1e-7, max_steps=400000)
+
+    O.lib()
+    main_threads = O.num_threads()
+    idx = np.arange(0, len(x0), every)
+    work = [(int(x0[i]), int(y0[i])) for i in idx]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(solve, work))
+    dt = time.perf_counter() - t0
+    O.set_threads(main_threads)
+    lu = sum(float(r.steps.sum()) * S.SIDE ** 2 for r in res)
+    return dict(value=round(len(work) / dt, 2), unit="patches/s", cores=threads, kind="oracle",
+                cpu_model=_cpu_model(),
+                sample=f"{len(work)} of {len(x0)} test patches (every {every}-th), {dt:.1f} s",
+                mlups=round(lu / dt / 1e6, 1))
+
+
+def bench_surrogate(n_test=65536, cpu=False):
     """The learned K_eff path on a test set of 32 x 32 patches (about 90% from
     the training distribution, 10% outside it): network, network + batched
     LBM fallback for flagged patches, and batched LBM alone; K_eff error of
-    the network against the LBM."""
+    the network against the LBM; with cpu, the oracle on a sample beside it."""
     from paper_1312_0195_amd import surrogate as S
     from paper_1312_0195_amd import train_surrogate as T
     if not os.path.exists(T.DEFAULT_MODEL):
@@ -342,7 +376,8 @@ def bench_surrogate(n_test=65536):
                 by_n_sym={k: dict(p50=v["p50"], p95=v["p95"], patches_per_s_network=v["patches_per_s"])
                           for k, v in r["keff_error_in_range_by_n_sym"].items()},
                 keff_rel_error_all_with_fallback=r["keff_error_combined_all"],
-                keff_rel_error_geometric_mean_p50=r["keff_error_geometric_mean_in_range"]["p50"])
+                keff_rel_error_geometric_mean_p50=r["keff_error_geometric_mean_in_range"]["p50"],
+                **({"cpu_baseline": cpu_baseline_surrogate(big, x0, y0)} if cpu else {}))
 
 
 D3Q19_BYTES_PER_LU = 156  # 19 x 4 B read + 19 x 4 B written + 4 B drag coefficient
@@ -646,7 +681,7 @@ def main():
     if not args.no_seeds:
         result["seeds"] = bench_seeds(L, torch, min(args.steps, 6000), args.no_local)
     if not args.no_surrogate and not args.no_local:
-        result["keff_surrogate"] = bench_surrogate()
+        result["keff_surrogate"] = bench_surrogate(cpu=not args.no_cpu)
     if not args.no_d3q19:
         result["d3q19"] = bench_d3q19(L, torch)
     if not args.no_cpu:
