@@ -485,8 +485,22 @@ __global__ __launch_bounds__(256) void k3_reduce(const double *__restrict__ part
 {
     __shared__ double red[3][4];
     double s[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < n; i += 256)
-        for (int k = 0; k < 3; ++k) s[k] += partials[3 * i + k];
+    // each thread adds its partials in index order, reading 8 of them ahead
+    constexpr int kAhead = 8;
+    for (int i0 = threadIdx.x; i0 < n; i0 += kAhead * 256) {
+        double v[kAhead][3];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int i = min(i0 + u * 256, n - 1);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[u][k] = partials[3 * i + k];
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (i0 + u * 256 < n)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s[k] += v[u][k];
+    }
     for (int k = 0; k < 3; ++k) s[k] = wave_sum(s[k]);
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
