@@ -150,9 +150,12 @@ void lbm_destroy(lbm_handle *h);
  *   kyy = nu ubar2_y / g.
  * All items of one call run in one persistent launch; when a call mixes sides
  * that leave one cell per thread with larger ones, in two launches side by
- * side, the second on a stream the library owns (one per device, default
- * priority), forked from and joined back to `stream`, so the call stays
- * ordered on `stream` like a single launch.
+ * side on streams the library owns (default priority, created on first use
+ * and kept per device), forked from and joined back to `stream`, so the call
+ * stays ordered on `stream` like a single launch. On a 256-CU device the two
+ * streams carry complementary CU masks, the single-cell launch getting a
+ * share of the CUs in proportion to its share of the cells (a multiple of 32
+ * CUs, 4 per XCD), so that neither launch waits for the other's CUs.
  * ------------------------------------------------------------------------- */
 
 typedef struct {
@@ -192,12 +195,15 @@ typedef struct {
 /* Start order of the local problems. An item's step count varies by orders
  * of magnitude between patches, so a batch ends when its slowest items end.
  * LBM_SCHEDULE_COST starts the items of each side in descending order of a
- * predicted cost, max(ln mean kappa, 0) + 1.5 sd(ln kappa) over the patch (a
- * high mean permeability relaxes slowly, on the time scale kappa / (eps nu)
- * of the drag term; a strongly heterogeneous patch has nearly blocked
- * directions whose small velocities converge slowly), computed by a device
- * pre-pass and binned in steps of 1/2 (ties in any order), so the long items
- * start first and the short ones fill in behind them. */
+ * predicted cost, ln(t_drag + t_pres) + sd(ln kappa) over the patch: a
+ * permeable patch relaxes slowly, on the time scale t_drag = mean kappa /
+ * (eps nu) of the drag term; a nearly impermeable one too, since where the
+ * drag dominates the density diffuses with coefficient c_s^2 kappa / (eps nu),
+ * t_pres = side^2 eps nu / (pi^2 c_s^2 kappa) with the geometric mean of
+ * kappa; a strongly heterogeneous patch has nearly blocked directions whose
+ * small velocities converge slowly. Computed by a device pre-pass and binned
+ * in steps of 1/4 (ties in any order), so the long items start first and the
+ * short ones fill in behind them. */
 enum {
     LBM_SCHEDULE_GIVEN = 0, /* the order of the patch arrays (within a side) */
     LBM_SCHEDULE_COST = 1   /* longest predicted first */

@@ -38,10 +38,12 @@
 //  * Within a side, items start in the order given or (LBM_SCHEDULE_COST)
 //    longest predicted first: step counts span orders of magnitude, and a
 //    long item that starts late sets the end of the whole batch. The
-//    prediction combines the patch's mean permeability and the spread of
-//    its logarithm (k_local_cost); a pre-pass bins it and counting-sorts the
-//    item list on the device.
+//    prediction adds the patch's two slowest relaxation times, the drag
+//    relaxation of a permeable patch and the pressure diffusion of a nearly
+//    impermeable one, and weighs in the spread of ln kappa (k_local_cost); a
+//    pre-pass bins it and counting-sorts the item list on the device.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -516,15 +518,25 @@ __global__ void k_local_prefill(int n, const int *__restrict__ mask, double *__r
 // ---- start order (LBM_SCHEDULE_COST) --------------------------------------
 // Key of an item: its side class in the high part (classes keep their
 // ranges), then the bin of its predicted cost, largest first. The prediction
-// is max(ln mean kappa, 0) + 1.5 sd(ln kappa) over the patch: a high mean
-// permeability means a slow relaxation of the mean flow (time scale
-// kappa / (eps nu)), and strong heterogeneity means nearly blocked directions
-// whose tiny velocities converge slowly; kCostBins bins of width 1/2.
+// is the logarithm of the sum of the two slowest relaxation times of the
+// Brinkman flow in the patch, plus the spread sd(ln kappa):
+//  * the drag relaxation of the mean flow, kappa / (eps nu), with the
+//    arithmetic mean of kappa: a permeable patch relaxes slowly;
+//  * the diffusion of pressure across the patch. Where the drag dominates,
+//    the momentum follows the pressure gradient, j = -(kappa / (eps nu))
+//    c_s^2 grad rho, so the density obeys a diffusion equation with
+//    coefficient c_s^2 kappa / (eps nu), and its slowest mode on a side S
+//    decays on the time scale S^2 eps nu / (pi^2 c_s^2 kappa), with the
+//    geometric mean of kappa: a nearly impermeable patch relaxes slowly too;
+//  * strong heterogeneity adds nearly blocked directions whose tiny
+//    velocities converge slowly.
+// kCostBins bins of width 1/4.
 constexpr int kCostBins = 64;
 
 __global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ items,
                                                     const ClassDesc *__restrict__ classes, int nclasses,
                                                     const double *__restrict__ field, int fnx, int fny,
+                                                    double inv_eps_nu, double pdiff,
                                                     int *__restrict__ keys, int *__restrict__ hist)
 {
     __shared__ double red[3][4];
@@ -554,10 +566,14 @@ __global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ ite
     const double mean = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) * inv;
     const double ml = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) * inv;
     const double var = ((red[2][0] + red[2][1]) + (red[2][2] + red[2][3])) * inv - ml * ml;
-    const double score = fmax(log(mean), 0.0) + 1.5 * sqrt(fmax(var, 0.0));
+    // relaxation times: drag of the mean flow, pressure diffusion (pdiff =
+    // eps nu / (pi^2 c_s^2))
+    const double t_drag = mean * inv_eps_nu;
+    const double t_pres = (double)n * pdiff / exp(ml);
+    const double score = log(t_drag + t_pres) + sqrt(fmax(var, 0.0));
     int bin;
     if (isfinite(score))
-        bin = min(kCostBins - 1, (int)(2.0 * score));
+        bin = max(0, min(kCostBins - 1, (int)(4.0 * score)));
     else
         bin = (score > 0.0) ? kCostBins - 1 : 0;  // +inf: a cell without drag, slowest; NaN: negative mean,
                                                   // the item ends at its first check (non-finite)
@@ -660,8 +676,51 @@ hipStream_t side_stream()
     return streams[dev];
 }
 
+// Two streams per device with complementary CU masks, for running the two
+// launches of a mixed call on disjoint sets of CUs: a launch of one
+// workgroup per CU (the largest sides) otherwise takes every CU at the start,
+// and the single-cell launch beside it only gets the CUs it frees at its end.
+// On a 256-CU part the mask bits interleave the eight XCDs (CU i lies on XCD
+// i % 8), and a mask that leaves an XCD without CUs makes launches fail; the
+// single-cell stream therefore gets k of the 32 CUs of every XCD, spread
+// evenly over them (k a multiple of kSplitStep), the other stream the rest.
+// Created on first use of each k and kept for the life of the process.
+constexpr int kSplitStep = 4;
+
+bool split_streams(int k, hipStream_t *multi, hipStream_t *single)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64][32 / kSplitStep][2] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    if (device_cu_count() != 256 || k < kSplitStep || k > 32 - kSplitStep || k % kSplitStep) return false;
+    const int slot = k / kSplitStep - 1;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev][slot][0]) {
+        uint32_t mm[8] = {}, ms[8] = {};
+        for (int i = 0; i < 256; ++i) {
+            const int l = i / 8;  // position of CU i within its XCD
+            const bool to_single = ((l + 1) * k) / 32 != (l * k) / 32;
+            (to_single ? ms : mm)[i / 32] |= 1u << (i % 32);
+        }
+        hipStream_t a = nullptr, b = nullptr;
+        if (hipExtStreamCreateWithCUMask(&a, 8, mm) != hipSuccess) return false;
+        if (hipExtStreamCreateWithCUMask(&b, 8, ms) != hipSuccess) {
+            (void)hipStreamDestroy(a);
+            return false;
+        }
+        streams[dev][slot][0] = a;
+        streams[dev][slot][1] = b;
+    }
+    *multi = streams[dev][slot][0];
+    *single = streams[dev][slot][1];
+    return true;
+}
+
+// cu_budget: the CUs the launch's stream may use (0: all of them); the grid
+// holds no more workgroups than fit on them at once.
 template <int T, typename P, int CPT>
-lbm_status launch_local_c(const LocalArgs &a, size_t lds_bytes, int grid, hipStream_t stream)
+lbm_status launch_local_c(const LocalArgs &a, size_t lds_bytes, int grid, hipStream_t stream, int cu_budget)
 {
     if (lds_bytes > 64 * 1024)
         LBM_HIP(hipFuncSetAttribute((const void *)k_local<T, P, CPT>,
@@ -669,18 +728,19 @@ lbm_status launch_local_c(const LocalArgs &a, size_t lds_bytes, int grid, hipStr
     int occ = 0;
     LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_local<T, P, CPT>, T, lds_bytes));
     if (occ < 1) return set_error(LBM_EINVAL, "lbm_local_keff: tile does not fit on a CU");
-    const int blocks = std::min(grid, device_cu_count() * occ);
+    const int blocks = std::min(grid, (cu_budget > 0 ? cu_budget : device_cu_count()) * occ);
     hipLaunchKernelGGL((k_local<T, P, CPT>), dim3(blocks), dim3(T), lds_bytes, stream, a);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
 
 template <int T, typename P>
-lbm_status launch_local(const LocalArgs &a, size_t lds_bytes, int grid, int cpt, hipStream_t stream)
+lbm_status launch_local(const LocalArgs &a, size_t lds_bytes, int grid, int cpt, hipStream_t stream,
+                        int cu_budget = 0)
 {
-    if (cpt <= 1) return launch_local_c<T, P, 1>(a, lds_bytes, grid, stream);
-    if (cpt <= 2) return launch_local_c<T, P, 2>(a, lds_bytes, grid, stream);
-    return launch_local_c<T, P, kCPT>(a, lds_bytes, grid, stream);
+    if (cpt <= 1) return launch_local_c<T, P, 1>(a, lds_bytes, grid, stream, cu_budget);
+    if (cpt <= 2) return launch_local_c<T, P, 2>(a, lds_bytes, grid, stream, cu_budget);
+    return launch_local_c<T, P, kCPT>(a, lds_bytes, grid, stream, cu_budget);
 }
 
 }  // namespace
@@ -818,8 +878,10 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
         int *d_hist = d_counters + kMaxClasses, *d_cursor = d_hist + kHist;
         int *d_keys = reinterpret_cast<int *>(ws + L.off_keys);
         int4 *d_sorted = reinterpret_cast<int4 *>(ws + L.off_sorted);
+        const double kPi = 3.14159265358979323846;
         hipLaunchKernelGGL(k_local_cost, dim3(ni), dim3(256), 0, stream, d_items, d_classes,
-                           (int)classes.size(), d_kappa_field, fnx, fny, d_keys, d_hist);
+                           (int)classes.size(), d_kappa_field, fnx, fny, 1.0 / (lp->eps * lp->nu),
+                           lp->eps * lp->nu * 3.0 / (kPi * kPi), d_keys, d_hist);
         LBM_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_local_scan, dim3(1), dim3(256), 0, stream, d_hist, d_cursor,
                            (int)classes.size() * kCostBins);
@@ -919,7 +981,7 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
         LBM_HIP(hipMemcpyAsync(d_esc, esc.data(), sizeof(ClassDesc) * esc.size(), hipMemcpyHostToDevice, stream));
         LBM_HIP(hipMemsetAsync(d_esc_counters, 0, sizeof(int) * esc.size(), stream));
     }
-    auto launch_group = [&](int first, int count, hipStream_t st) -> lbm_status {
+    auto launch_group = [&](int first, int count, hipStream_t st, int cu_budget) -> lbm_status {
         LocalArgs g = a;
         g.classes = d_grouped + first;
         g.nclasses = count;
@@ -937,11 +999,11 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
         const int cpt = cmax <= 1 ? 1 : (cmax <= 2 ? 2 : 4);
         const int grid = std::max(1, need);
         if (f64)
-            return (T == 256) ? launch_local<256, double>(g, lds, grid, cpt, st)
-                              : launch_local<512, double>(g, lds, grid, cpt, st);
-        if (T == 256) return launch_local<256, float>(g, lds, grid, cpt, st);
-        if (T == 512) return launch_local<512, float>(g, lds, grid, cpt, st);
-        return launch_local<1024, float>(g, lds, grid, cpt, st);
+            return (T == 256) ? launch_local<256, double>(g, lds, grid, cpt, st, cu_budget)
+                              : launch_local<512, double>(g, lds, grid, cpt, st, cu_budget);
+        if (T == 256) return launch_local<256, float>(g, lds, grid, cpt, st, cu_budget);
+        if (T == 512) return launch_local<512, float>(g, lds, grid, cpt, st, cu_budget);
+        return launch_local<1024, float>(g, lds, grid, cpt, st, cu_budget);
     };
     // The FP64 re-run, queued on `stream` after the FP32 launch(es): a
     // persistent launch over the re-run queues, whose workgroups leave at
@@ -965,29 +1027,53 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     const int n_single = (int)grouped.size() - n_multi;
     hipStream_t side = (n_multi > 0 && n_single > 0) ? side_stream() : nullptr;
     if (!side) {
-        const lbm_status st = launch_group(0, (int)grouped.size(), stream);
+        const lbm_status st = launch_group(0, (int)grouped.size(), stream, 0);
         if (st != LBM_OK) return st;
         return launch_esc();
     }
-    hipEvent_t fork = nullptr, join = nullptr;
+    // CUs for the single-cell launch in proportion to its share of the cells
+    // (step counts are not known here); 256-CU parts only, else both launches
+    // share all CUs
+    double w_multi = 0.0, w_single = 0.0;
+    for (int i = 0; i < (int)grouped.size(); ++i)
+        (i < n_multi ? w_multi : w_single) += (double)grouped[i].count * grouped[i].side * grouped[i].side;
+    const int k = (int)std::lround(w_single / (w_multi + w_single) * (32.0 / kSplitStep)) * kSplitStep;
+    hipStream_t s_multi = stream, s_single = side;
+    int cu_multi = 0, cu_single = 0;
+    if (split_streams(k, &s_multi, &s_single)) {
+        cu_single = 8 * k;
+        cu_multi = 256 - cu_single;
+    } else {
+        s_multi = stream;
+        s_single = side;
+    }
+    hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
     LBM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&join2, hipEventDisableTiming) != hipSuccess) {
         (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
         return set_error(LBM_EDEVICE, std::string(fn) + "hipEventCreateWithFlags failed");
     }
     lbm_status st = LBM_OK;
     hipError_t e = hipEventRecord(fork, stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s_single, fork, 0);
+    if (e == hipSuccess && s_multi != stream) e = hipStreamWaitEvent(s_multi, fork, 0);
     if (e == hipSuccess) {
-        st = launch_group(0, n_multi, stream);
-        if (st == LBM_OK) st = launch_group(n_multi, n_single, side);
+        st = launch_group(0, n_multi, s_multi, cu_multi);
+        if (st == LBM_OK) st = launch_group(n_multi, n_single, s_single, cu_single);
         // join even after a failed launch, so the caller's stream never runs
-        // ahead of work queued on the side stream
-        e = hipEventRecord(join, side);
+        // ahead of work queued on the other streams
+        e = hipEventRecord(join, s_single);
         if (e == hipSuccess) e = hipStreamWaitEvent(stream, join, 0);
+        if (e == hipSuccess && s_multi != stream) {
+            e = hipEventRecord(join2, s_multi);
+            if (e == hipSuccess) e = hipStreamWaitEvent(stream, join2, 0);
+        }
     }
     (void)hipEventDestroy(fork);
     (void)hipEventDestroy(join);
+    (void)hipEventDestroy(join2);
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return hip_check(e, "lbm_local_keff: stream fork/join");
     return launch_esc();
