@@ -203,7 +203,10 @@ typedef struct {
  * kappa; a strongly heterogeneous patch has nearly blocked directions whose
  * small velocities converge slowly. Computed by a device pre-pass and binned
  * in steps of 1/4 (ties in any order), so the long items start first and the
- * short ones fill in behind them. */
+ * short ones fill in behind them. The largest sides of a call (those that
+ * fill a workgroup with more than one cell per thread) share one queue, with
+ * the prediction lowered by 2 ln(side / largest side) for their cheaper
+ * steps. */
 enum {
     LBM_SCHEDULE_GIVEN = 0, /* the order of the patch arrays (within a side) */
     LBM_SCHEDULE_COST = 1   /* longest predicted first */

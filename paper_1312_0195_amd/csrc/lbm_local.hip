@@ -35,7 +35,9 @@
 //    side's queue is empty and all slots are idle the workgroup moves on to
 //    the next side. Every item runs at most max_steps steps, so every
 //    workgroup reaches the end of the queues and exits.
-//  * Within a side, items start in the order given or (LBM_SCHEDULE_COST)
+//  * The largest sides (one item per workgroup, more than one cell per
+//    thread) share one queue; each item takes its own side from its entry.
+//  * Within a queue, items start in the order given or (LBM_SCHEDULE_COST)
 //    longest predicted first: step counts span orders of magnitude, and a
 //    long item that starts late sets the end of the whole batch. The
 //    prediction adds the patch's two slowest relaxation times, the drag
@@ -70,6 +72,7 @@ struct ClassDesc {
     int cells_per_thread;
     int begin, count;  // item range in the sorted item list
     int esc_ok;        // FP32 items of this side may be handed to the FP64 re-run
+    int merged;        // items of several sides (side: the largest); each item's own side in its int4
 };
 
 struct LocalArgs {
@@ -243,6 +246,7 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
     bool over_budget = false;  // FP32 item past esc_steps that cannot be re-run in FP64
     double prev_x = 0.0, prev_y = 0.0;
     int out = 0, x0 = 0, y0 = 0;
+    int item_side = 0;  // side of the slot's item (classes of merged sides)
     P hegx = 0, hegy = 0, tgx = 0, tgy = 0;
     P Ux = 0, Uy = 0;  // reference momentum of the rebased state
     double hegx_d = 0.0, hegy_d = 0.0;
@@ -255,8 +259,11 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
 
     while (true) {
         const ClassDesc cd = a.classes[cls];
-        const int S = cd.side, G = cd.slot_threads, C = cd.cells_per_thread;
-        const int S2 = S * S;
+        const int G = cd.slot_threads, C = cd.cells_per_thread;
+        // a merged class has one slot (G = T), so the slot's LDS starts at 0
+        // whatever the side, and the side is the item's from its claim on
+        int S = cd.merged ? item_side : cd.side;
+        int S2 = S * S;
         const int slot = tid / G, lt = tid - slot * G;
         const bool in_slot = slot < cd.nslots;
         P *A = lds + (size_t)(in_slot ? slot : 0) * 8 * S2;
@@ -275,6 +282,11 @@ __global__ __launch_bounds__(T, (CPT == 1 && sizeof(P) == 4 ? 8 : 1)) void k_loc
                 x0 = it.x;
                 y0 = it.y;
                 out = it.w;
+                item_side = it.z;
+                if (cd.merged) {
+                    S = it.z;
+                    S2 = S * S;
+                }
                 const int drive = out & 1;
                 hegx = drive == 0 ? kc.heg : P(0);
                 hegy = drive == 1 ? kc.heg : P(0);
@@ -570,16 +582,19 @@ __global__ __launch_bounds__(256) void k_local_cost(const int4 *__restrict__ ite
     // eps nu / (pi^2 c_s^2))
     const double t_drag = mean * inv_eps_nu;
     const double t_pres = (double)n * pdiff / exp(ml);
-    const double score = log(t_drag + t_pres) + sqrt(fmax(var, 0.0));
+    int cls = 0;
+    for (int c = 0; c < nclasses; ++c)
+        if (item >= classes[c].begin && item < classes[c].begin + classes[c].count) cls = c;
+    // in a class of merged sides a step of a smaller side costs less, in
+    // proportion to its cells
+    const double score = log(t_drag + t_pres) + sqrt(fmax(var, 0.0)) +
+                         (classes[cls].merged ? 2.0 * log((double)S / (double)classes[cls].side) : 0.0);
     int bin;
     if (isfinite(score))
         bin = max(0, min(kCostBins - 1, (int)(4.0 * score)));
     else
         bin = (score > 0.0) ? kCostBins - 1 : 0;  // +inf: a cell without drag, slowest; NaN: negative mean,
                                                   // the item ends at its first check (non-finite)
-    int cls = 0;
-    for (int c = 0; c < nclasses; ++c)
-        if (item >= classes[c].begin && item < classes[c].begin + classes[c].count) cls = c;
     const int key = cls * kCostBins + (kCostBins - 1 - bin);
     keys[item] = key;
     atomicAdd(&hist[key], 1);
@@ -852,6 +867,32 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     // drop classes without items (all drives masked)
     classes.erase(std::remove_if(classes.begin(), classes.end(), [](const ClassDesc &c) { return c.count == 0; }),
                   classes.end());
+    // The largest sides (one item per workgroup over all its threads, more
+    // than one cell per thread, never eligible for the FP64 re-run, whose
+    // layout cannot hold them) share one queue, so that their items start in
+    // one longest-predicted-first order across the sides: in queues of their
+    // own, a long item of a smaller side waits until the larger side's queue
+    // is empty. Their items lie next to each other in the list (sorted by
+    // side), and each takes its own side from its entry.
+    if (!f64) {
+        std::vector<ClassDesc> m;
+        bool prev_whole = false;
+        for (const ClassDesc &c : classes) {
+            const int cells = c.side * c.side;
+            const int ge = std::min(kEscThreads, std::max(64, pow2_at_least(cells)));
+            const bool whole = c.nslots == 1 && c.slot_threads == T && c.cells_per_thread > 1 &&
+                               ((cells + ge - 1) / ge > kCPT || (size_t)64 * cells > (size_t)budget);
+            if (whole && prev_whole) {
+                m.back().count += c.count;
+                m.back().merged = 1;
+                m.back().cells_per_thread = std::max(m.back().cells_per_thread, c.cells_per_thread);
+            } else {
+                m.push_back(c);
+            }
+            prev_whole = whole;
+        }
+        classes.swap(m);
+    }
     if ((int)classes.size() > kMaxClasses) return set_error(LBM_EINVAL, std::string(fn) + "too many sides");
     for (const int4 &it : items)
         if (it.x < 0 || it.y < 0) return set_error(LBM_EINVAL, std::string(fn) + "origins must be >= 0");
@@ -1036,7 +1077,8 @@ extern "C" lbm_status lbm_local_keff(const lbm_local_params *lp, int32_t n_patch
     // share all CUs
     double w_multi = 0.0, w_single = 0.0;
     for (int i = 0; i < (int)grouped.size(); ++i)
-        (i < n_multi ? w_multi : w_single) += (double)grouped[i].count * grouped[i].side * grouped[i].side;
+        for (int j = grouped[i].begin; j < grouped[i].begin + grouped[i].count; ++j)
+            (i < n_multi ? w_multi : w_single) += (double)items[j].z * items[j].z;
     const int k = (int)std::lround(w_single / (w_multi + w_single) * (32.0 / kSplitStep)) * kSplitStep;
     hipStream_t s_multi = stream, s_single = side;
     int cu_multi = 0, cu_single = 0;
