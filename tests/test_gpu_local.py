@@ -157,6 +157,27 @@ def test_local_mixed_call_matches_calls_per_side(L):
         assert np.array_equal(one.steps, both.steps[m]) and np.array_equal(one.flags, both.flags[m]), s
 
 
+def test_local_largest_sides_share_a_queue(L):
+    # Sides 48 and 64 each fill a workgroup with more than one cell per thread
+    # and share one queue, every item taking its own side from its entry; in
+    # both start orders each item must come out as in a call of its side
+    # alone.
+    field = I.lognormal_kappa(128, 128, 1.5, 6.0, seed=21)
+    rng = np.random.default_rng(22)
+    sides = rng.choice([48, 64], 24).astype(np.int32)
+    x0 = rng.integers(0, 128, 24).astype(np.int32)
+    y0 = rng.integers(0, 128, 24).astype(np.int32)
+    kw = dict(tol=GPU_TOL, check_every=100, max_steps=6000)
+    alone = {s: L.local_keff(field, x0[sides == s], y0[sides == s], sides[sides == s], TAU, EPS, NU, G, **kw)
+             for s in (48, 64)}
+    for sched in (L.LBM_SCHEDULE_GIVEN, L.LBM_SCHEDULE_COST):
+        both = L.local_keff(field, x0, y0, sides, TAU, EPS, NU, G, schedule=sched, **kw)
+        for s, one in alone.items():
+            m = sides == s
+            assert np.array_equal(one.keff, both.keff[m], equal_nan=True), (sched, s)
+            assert np.array_equal(one.steps, both.steps[m]) and np.array_equal(one.flags, both.flags[m]), (sched, s)
+
+
 def test_local_schedule_f64_state(L):
     # FP64 items (sides up to 45) in both start orders: identical results
     field = I.lognormal_kappa(96, 96, 2.0, 5.0, seed=8)
