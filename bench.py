@@ -45,7 +45,7 @@ FLOPS_PER_LU = 65
 FP32_FLOPS_PER_LU_LOCAL = 65
 FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (published; counts packed FP32 issue)
 FP32_UNPACKED_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2: packed FP32 is not used
-DEPTH = 6          # time steps per launch of the fine-step kernel (FP32 state)
+DEPTH = 7          # time steps per launch of the fine-step kernel (FP32 state, FP32 arithmetic)
 # The fine step as benchmarked: FP32 state and FP32 collision arithmetic
 # (LBM_F32_FAST), within 2.6e-6 of the FP64-state solver in relative L2 of
 # the velocity after the workload's 20 000 steps (the target is 1e-5);

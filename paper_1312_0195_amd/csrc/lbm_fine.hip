@@ -33,6 +33,8 @@
 // types; FP32 storage only rounds the nine values written per cell.
 #include <hip/hip_runtime.h>
 
+#include <array>
+
 #include <cmath>
 #include <cstring>
 #include <algorithm>
@@ -480,6 +482,16 @@ template <> struct TileDA<float, 4, float> : TileShape<LBM_TILE4F> {};
 #define LBM_TILE2F 96, 18, 768  // two-step launches (us, 2048^2): 66.0 against 74.3 for 64 x 64 on 1024
 #endif
 template <> struct TileDA<float, 2, float> : TileShape<LBM_TILE2F> {};
+// Seven steps per launch, FP32 collision arithmetic only (the depth the
+// launch planner takes for most steps of that path): per launch on 2048^2
+// (us) 36 x 28 on 768 threads 98.8 (14.1 per step against 14.9 at six
+// steps), 48 x 22 99.9, 40 x 26 101.3, 42 x 24 102.7, 44 x 22 104.7,
+// 32 x 32 105.4; eight steps with 30 x 30 120.4.
+constexpr int kDeeper = 7;
+#ifndef LBM_TILE7F
+#define LBM_TILE7F 36, 28, 768
+#endif
+template <> struct TileDA<float, kDeeper, float> : TileShape<LBM_TILE7F> {};
 
 // D time steps per launch (temporal blocking). Phase 1 takes step t on the
 // workgroup's tile plus a (D - 1)-cell halo, pulling from HBM and keeping the
@@ -1046,8 +1058,6 @@ struct StepDFn {
     template <int D>
     static void launch(const lbm_handle *h)
     {
-        constexpr int TX = TileD<R, D>::TX, TY = TileD<R, D>::TY, BS = TileD<R, D>::BS;
-        const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
         if constexpr (std::is_same<R, float>::value && PK != 0) {
             if (h->p.pop_dtype == LBM_F32_FAST) {
                 using TF = TileDA<R, D, float>;
@@ -1064,22 +1074,53 @@ struct StepDFn {
                 return;
             }
         }
-        hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D>), dim3(ntx * nty), dim3(BS), 0, h->stream,
-                           step_args<R>(h));
+        if constexpr (D != kDeeper) {  // seven steps: FP32 collision arithmetic only
+            constexpr int TX = TileD<R, D>::TX, TY = TileD<R, D>::TY, BS = TileD<R, D>::BS;
+            const int ntx = (h->p.nx + TX - 1) / TX, nty = (h->p.ny + TY - 1) / TY;
+            hipLaunchKernelGGL((k_stepd<R, W, PK, FF, D>), dim3(ntx * nty), dim3(BS), 0, h->stream,
+                               step_args<R>(h));
+        }
     }
     static void run(const lbm_handle *h, int depth)
     {
+        if (depth == kDeeper) return launch<kDeeper>(h);
         if (depth == kDeep) return launch<kDeep>(h);
         if (depth == 4) return launch<4>(h);
         launch<2>(h);
     }
 };
 
-// Steps per launch: the deepest available depth that fits before the next
-// check (or the end); 1 runs the single-step kernel.
+// Steps per launch before the next check (or the end), `room` steps away; 1
+// runs the single-step kernel. Every depth gives the same state bit for bit,
+// so the choice is one of time only. With FP32 collision arithmetic, whose
+// seven-step kernel takes fewer microseconds per step than the six-step one,
+// the plan of launches that covers `room` in the least time by the launch
+// costs measured on 2048^2 (us: 1 step 50, 2: 66.0, 4: 76.8, 6: 89.2,
+// 7: 98.8): seven-step launches while more than 60 steps remain, then the
+// best mix for the rest (e.g. 100 = 10 x 7 + 5 x 6, 1434 us against 1505 for
+// 16 x 6 + 4; 20 = 7 + 7 + 6, 287 us against 334 for 6 + 6 + 6 + 2).
+// Otherwise the deepest depth that fits.
 int launch_depth(const lbm_handle *h, int64_t room)
 {
-    (void)h;
+    if (h->p.pop_dtype == LBM_F32_FAST) {
+        static const std::array<signed char, 61> first = [] {
+            const int depth[5] = {kDeeper, kDeep, 4, 2, 1};
+            const double cost[5] = {98.8, 89.2, 76.8, 66.0, 50.0};
+            std::array<double, 61> best{};
+            std::array<signed char, 61> f{};
+            for (int r = 1; r <= 60; ++r) {
+                best[r] = 1e30;
+                for (int i = 0; i < 5; ++i)
+                    if (depth[i] <= r && cost[i] + best[r - depth[i]] < best[r]) {
+                        best[r] = cost[i] + best[r - depth[i]];
+                        f[r] = (signed char)depth[i];
+                    }
+            }
+            return f;
+        }();
+        if (room > 60) return kDeeper;
+        return room >= 1 ? first[room] : 1;
+    }
     if (room >= kDeep) return kDeep;
     if (room >= 4) return 4;
     return room >= 2 ? 2 : 1;

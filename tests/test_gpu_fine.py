@@ -152,18 +152,20 @@ def test_fine_converges_to_oracle_steady_state(L):
 
 @pytest.mark.parametrize("nx,ny,walls", [(2048, 96, 1), (130, 70, 0), (200, 37, 1), (64, 33, 1),
                                          (5, 3, 0), (3, 40, 1)])
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "f32_fast"])
 def test_multi_step_launches_match_single_steps_bitwise(L, nx, ny, walls, dtype):
     """lbm_step advances several steps per launch (temporal blocking in LDS:
-    6, 4 or 2 steps, FP32 or FP64 state) whenever no check falls in between;
-    the state must equal that of single-step launches bit for bit (ragged
-    tiles, walls, periodic y, grids smaller than the halo)."""
-    dt = L.LBM_F64 if dtype == "f64" else L.LBM_F32_SHIFTED
+    7 (FP32 collision arithmetic only), 6, 4 or 2 steps, FP32 or FP64 state)
+    whenever no check falls in between; the state must equal that of
+    single-step launches bit for bit (ragged tiles, walls, periodic y, grids
+    smaller than the halo)."""
+    dt = {"f64": L.LBM_F64, "f32": L.LBM_F32_SHIFTED, "f32_fast": L.LBM_F32_FAST}[dtype]
     k = I.lognormal_kappa(nx, ny, 1.5, 6.0, seed=11)
     p = L.make_params(nx, ny, 0.7, 0.4, 0.1, 1.0, 1e-6, 3e-7, walls, dt)
     a = L.FineSolver(p, k)
     b = L.FineSolver(p, k)
-    for n in (37, 11, 3):      # FP32: 6x6 + 1, 6 + 4 + 1, 2 + 1 steps per launch
+    for n in (37, 11, 3):      # FP32: 6x6 + 1, 6 + 4 + 1, 2 + 1 steps per launch;
+                               # FP32 arithmetic: 7 + 5x6, 7 + 4, 2 + 1
         a.step(n)
     for _ in range(51):
         b.step(1)              # single-step launches only
@@ -194,6 +196,32 @@ def test_multi_step_launches_bitwise_all_kernel_forms(L, scheme, perm_kind, forc
     a.step(24)                 # 6 x 4 steps per launch
     a.step(5)                  # 4 + 1
     for _ in range(29):
+        b.step(1)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+
+
+@pytest.mark.parametrize("perm_kind,force,gy", [(4, True, 3e-7), (1, True, 3e-7), (4, False, 3e-7),
+                                                (1, False, 0.0)])
+def test_seven_step_launches_bitwise_other_forms(L, perm_kind, force, gy):
+    """FP32 collision arithmetic takes seven steps per launch where the plan
+    allows: tensor permeability, a per-cell force field, with and without a
+    drive along y (ragged tiles, periodic y), bit for bit as single steps."""
+    nx, ny = 150, 45
+    rng = np.random.default_rng(5)
+    if perm_kind == 4:
+        kxx = np.exp(rng.standard_normal((ny, nx)))
+        kyy = np.exp(rng.standard_normal((ny, nx)))
+        kxy = 0.2 * np.sqrt(kxx * kyy) * rng.uniform(-1, 1, (ny, nx))
+        k = np.stack([kxx, kxy, 0.5 * kxy, kyy], axis=-1)
+    else:
+        k = I.lognormal_kappa(nx, ny, 1.5, 6.0, seed=13)
+    f = 1e-6 * rng.standard_normal((ny, nx, 2)) if force else None
+    p = L.make_params(nx, ny, 0.9, 0.4, 0.1, 1.0, 1e-6, gy, 0, L.LBM_F32_FAST, perm_kind)
+    a = L.FineSolver(p, k, f)
+    b = L.FineSolver(p, k, f)
+    a.step(20)                 # 7 + 7 + 6
+    a.step(14)                 # 7 + 7
+    for _ in range(34):
         b.step(1)
     assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
 
