@@ -1095,7 +1095,7 @@ struct StepDFn {
 // so the choice is one of time only. With FP32 collision arithmetic, whose
 // seven-step kernel takes fewer microseconds per step than the six-step one,
 // the plan of launches that covers `room` in the least time by the launch
-// costs measured on 2048^2 (us: 1 step 50, 2: 66.0, 4: 76.8, 6: 89.2,
+// costs measured on 2048^2 (us: 1 step 54.5, 2: 66.0, 4: 76.8, 6: 89.2,
 // 7: 98.8): seven-step launches while more than 60 steps remain, then the
 // best mix for the rest (e.g. 100 = 10 x 7 + 5 x 6, 1434 us against 1505 for
 // 16 x 6 + 4; 20 = 7 + 7 + 6, 287 us against 334 for 6 + 6 + 6 + 2).
@@ -1105,7 +1105,7 @@ int launch_depth(const lbm_handle *h, int64_t room)
     if (h->p.pop_dtype == LBM_F32_FAST) {
         static const std::array<signed char, 61> first = [] {
             const int depth[5] = {kDeeper, kDeep, 4, 2, 1};
-            const double cost[5] = {98.8, 89.2, 76.8, 66.0, 50.0};
+            const double cost[5] = {98.8, 89.2, 76.8, 66.0, 54.5};
             std::array<double, 61> best{};
             std::array<signed char, 61> f{};
             for (int r = 1; r <= 60; ++r) {
